@@ -1,0 +1,562 @@
+"""Pins of the CPU oracle against facts fixed by the mathematics.
+
+None of these re-types the oracle's formulas: each compares it with a closed
+form, an exactness property, an invariance, an independent numpy
+construction (numpy Legendre series, complex-step derivatives, physical-space
+chain rule) or a structural identity (exact sequence), chosen so that a
+dropped term, a wrong sign or index, or a transposed operand fails at least
+one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+
+SCALAR, VECTOR = 0, 1
+MAT_SINCOSEXP, MAT_ROTDIAG, MAT_PLANEWAVE, ALPHA_SAMPLED = 0, 1, 2, 3
+
+
+def nominal_nodes():
+    n = np.zeros((27, 3))
+    for k in range(3):
+        for j in range(3):
+            for i in range(3):
+                n[i + 3 * j + 9 * k] = (0.5 * i, 0.5 * j, 0.5 * k)
+    return n
+
+
+def curved_nodes(seed, amp=0.08):
+    rng = np.random.default_rng(seed)
+    return nominal_nodes() + rng.uniform(-amp, amp, size=(27, 3))
+
+
+def run_fill(oracle_mod, problem, material, nodes, mat, N, Q, sK=1.0, sM=1.0):
+    nodes = np.asarray(nodes, dtype=np.float64).reshape(-1, 27, 3)
+    E = nodes.shape[0]
+    mat = np.asarray(mat, dtype=np.float64).reshape(E, -1)
+    if np.isscalar(Q):
+        Q = (Q, Q, Q)
+    out, off, st = oracle_mod.fill(problem, material, nodes, mat,
+                                   np.full(E, N, np.int32),
+                                   np.tile(np.asarray(Q, np.int32), (E, 1)), sK, sM)
+    assert (st == 0).all()
+    return [oracle_mod.blocks(out, off, e) for e in range(E)]
+
+
+# ---------------------------------------------------------------- G1
+@pytest.mark.parametrize("Q", [1, 2, 3, 5, 8, 12, 16, 24, 32, 40])
+def test_gauss_rule_matches_numpy_and_is_exact(oracle_mod, Q):
+    x, w = oracle_mod.gauss_legendre(Q)
+    xr, wr = npleg.leggauss(Q)
+    assert np.abs(x - xr).max() < 4e-15
+    assert np.abs(w - wr).max() < 4e-15
+    assert abs(w.sum() - 2.0) < 1e-14
+    for d in range(0, 2 * Q):
+        exact = 0.0 if d % 2 else 2.0 / (d + 1)
+        assert abs((w * x ** d).sum() - exact) < 1e-13 * max(1, Q)
+
+
+# ---------------------------------------------------------------- C1
+def _int(f, g, Q=12):
+    """Gauss sum, exact for the polynomial degrees used here (<= 2Q-1)."""
+    x, w = npleg.leggauss(Q)
+    return math.fsum(wi * f(xi) * g(xi) for xi, wi in zip(x, w))
+
+
+def test_one_d_closed_forms(oracle_mod):
+    phi, dphi, psi = oracle_mod.phi, oracle_mod.dphi, oracle_mod.psi
+    P = lambda m: (lambda t: phi(m, t))
+    D = lambda m: (lambda t: dphi(m, t))
+    S = lambda m: (lambda t: psi(m, t))
+    tol = 2e-14
+    assert abs(_int(P(0), P(0)) - 2 / 3) < tol
+    assert abs(_int(P(1), P(1)) - 2 / 3) < tol
+    assert abs(_int(P(0), P(1)) - 1 / 3) < tol
+    assert abs(_int(P(0), P(2)) + math.sqrt(6) / 6) < tol
+    assert abs(_int(P(1), P(2)) + math.sqrt(6) / 6) < tol
+    assert abs(_int(P(0), P(3)) - 1 / (3 * math.sqrt(10))) < tol
+    assert abs(_int(P(1), P(3)) + 1 / (3 * math.sqrt(10))) < tol
+    for m in range(4, 10):
+        assert abs(_int(P(0), P(m))) < tol and abs(_int(P(1), P(m))) < tol
+    for m in range(2, 10):
+        assert abs(_int(P(m), P(m)) - 2 / ((2 * m + 1) * (2 * m - 3))) < tol
+        assert abs(_int(P(m), P(m + 2)) + 1 / ((2 * m + 1) * math.sqrt((2 * m - 1) * (2 * m + 3)))) < tol
+        assert abs(_int(P(m), P(m + 1))) < tol
+    for m in range(0, 10):
+        for n in range(0, 10):
+            if m >= 2 and n >= 2:
+                assert abs(_int(D(m), D(n)) - (m == n)) < tol
+            assert abs(_int(S(m), S(n)) - (m == n)) < tol
+    assert abs(_int(D(0), D(0)) - 0.5) < tol
+    assert abs(_int(D(1), D(1)) - 0.5) < tol
+    assert abs(_int(D(0), D(1)) + 0.5) < tol
+    for m in range(2, 10):
+        assert abs(_int(D(0), D(m))) < tol and abs(_int(D(1), D(m))) < tol
+    # phi'_m is the derivative of phi_m (central difference, smooth polynomial)
+    h = 1e-5
+    for m in range(0, 10):
+        for t in (-0.9, -0.3, 0.2, 0.7):
+            fd = (phi(m, t + h) - phi(m, t - h)) / (2 * h)
+            assert abs(fd - dphi(m, t)) < 1e-8
+    # hierarchical: phi_m vanishes at both ends for m >= 2
+    for m in range(2, 10):
+        assert abs(phi(m, -1.0)) < 1e-15 and abs(phi(m, 1.0)) < 1e-15
+
+
+# ---------------------------------------------------------------- geometry
+def test_map_interpolates_nodes_and_jacobian_is_derivative(oracle_mod):
+    nodes = curved_nodes(3, 0.1)
+    for k in range(3):
+        for j in range(3):
+            for i in range(3):
+                x, _ = oracle_mod.geometry(nodes, i - 1.0, j - 1.0, k - 1.0)
+                assert np.abs(x - nodes[i + 3 * j + 9 * k]).max() < 1e-15
+    h = 1e-6
+    rng = np.random.default_rng(0)
+    for _ in range(10):
+        p = rng.uniform(-1, 1, 3)
+        _, J = oracle_mod.geometry(nodes, *p)
+        for c in range(3):
+            dp = np.zeros(3)
+            dp[c] = h
+            xp, _ = oracle_mod.geometry(nodes, *(p + dp))
+            xm, _ = oracle_mod.geometry(nodes, *(p - dp))
+            assert np.abs((xp - xm) / (2 * h) - J[:, c]).max() < 1e-8
+    _, J = oracle_mod.geometry(nominal_nodes(), 0.3, -0.2, 0.5)
+    assert np.abs(J - 0.5 * np.eye(3)).max() < 1e-15
+
+
+def test_rotdiag_material_spectrum(oracle_mod):
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((3, 3))
+    R, _ = np.linalg.qr(A)
+    k = rng.standard_normal(3)
+    x = rng.uniform(0, 1, 3)
+    eps = oracle_mod.permittivity(MAT_ROTDIAG, np.concatenate([R.reshape(-1), k]), x)
+    assert np.abs(eps - eps.T).max() < 1e-15
+    for a in range(3):
+        d = 1 + 0.5 * math.sin(k @ x + 2 * math.pi * a / 3)
+        assert np.abs(eps @ R[a] - d * R[a]).max() < 1e-14
+
+
+# ---------------------------------------------------------------- U1
+def _mass1(N):
+    """1-D integrals of phi_m phi_n from the closed forms."""
+    M = np.zeros((N, N))
+    M[0, 0] = M[1, 1] = 2 / 3
+    M[0, 1] = M[1, 0] = 1 / 3
+    if N > 2:
+        M[0, 2] = M[2, 0] = M[1, 2] = M[2, 1] = -math.sqrt(6) / 6
+    if N > 3:
+        M[0, 3] = M[3, 0] = 1 / (3 * math.sqrt(10))
+        M[1, 3] = M[3, 1] = -1 / (3 * math.sqrt(10))
+    for m in range(2, N):
+        M[m, m] = 2 / ((2 * m + 1) * (2 * m - 3))
+        if m + 2 < N:
+            M[m, m + 2] = M[m + 2, m] = -1 / ((2 * m + 1) * math.sqrt((2 * m - 1) * (2 * m + 3)))
+    return M
+
+
+def _stiff1(N):
+    K = np.eye(N)
+    K[0, 0] = K[1, 1] = 0.5
+    K[0, 1] = K[1, 0] = -0.5
+    return K
+
+
+def _grad1(N):
+    """phi'_m = sum_k D[k, m] psi_k (k < N-1)."""
+    D = np.zeros((N - 1, N))
+    D[0, 0] = -1 / math.sqrt(2)
+    D[0, 1] = 1 / math.sqrt(2)
+    for m in range(2, N):
+        D[m - 1, m] = 1.0
+    return D
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 6])
+def test_scalar_universal_matrix(oracle_mod, N):
+    (A,) = run_fill(oracle_mod, SCALAR, MAT_SINCOSEXP, nominal_nodes(), [0.0], N, N + 1)
+    M1, K1 = _mass1(N), _stiff1(N)
+    ref = 0.5 * (np.kron(np.kron(K1, M1), M1) + np.kron(np.kron(M1, K1), M1)
+                 + np.kron(np.kron(M1, M1), K1)) + 0.125 * np.kron(np.kron(M1, M1), M1)
+    assert np.abs(A - ref).max() < 1e-14
+
+
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_vector_universal_matrix(oracle_mod, N):
+    """Undeformed cube, eps = 1: curl coefficient J^T J / detJ = 2 I and mass
+    coefficient detJ J^-1 J^-T = I / 2; the blocks are Kronecker products of
+    1-D matrices, with the signs of the reference curl."""
+    (A,) = run_fill(oracle_mod, VECTOR, MAT_SINCOSEXP, nominal_nodes(), [0.0], N, N + 1)
+    M1, K1, D = _mass1(N), _stiff1(N), _grad1(N)
+    I = np.eye(N - 1)
+    G = D @ np.eye(N)  # psi-phi' coupling; int psi_k phi'_m = D[k, m]
+    kron = lambda a, b, c: np.kron(np.kron(a, b), c)
+    # 1-D factor matrices per axis for (test family, trial family)
+    # component g has psi on axis g, phi elsewhere; the curl of f e_g uses
+    # derivatives along the two other axes.
+    blocks = [[None] * 3 for _ in range(3)]
+    # diagonal blocks: curl.curl = sum over the two other axes of d_e f d_e g
+    blocks[0][0] = 2 * (kron(I, K1, M1) + kron(I, M1, K1)) + 0.5 * kron(I, M1, M1)
+    blocks[1][1] = 2 * (kron(K1, I, M1) + kron(M1, I, K1)) + 0.5 * kron(M1, I, M1)
+    blocks[2][2] = 2 * (kron(K1, M1, I) + kron(M1, K1, I)) + 0.5 * kron(M1, M1, I)
+    # curl(f e_u).curl(g e_v) = -d_v f d_u g; (f: psi(u) phi(v) phi(w); g: phi(u) psi(v) phi(w))
+    blocks[0][1] = -2 * kron(G, G.T, M1)
+    # curl(f e_u).curl(h e_w) = -d_w f d_u h
+    blocks[0][2] = -2 * kron(G, M1, G.T)
+    # curl(g e_v).curl(h e_w) = -d_w g d_v h
+    blocks[1][2] = -2 * kron(M1, G, G.T)
+    blocks[1][0] = blocks[0][1].T
+    blocks[2][0] = blocks[0][2].T
+    blocks[2][1] = blocks[1][2].T
+    ref = np.block(blocks)
+    assert A.shape == ref.shape
+    assert np.abs(A - ref).max() < 1e-14
+
+
+# ---------------------------------------------------------------- E1
+@pytest.mark.parametrize("N", [3, 4])
+def test_curved_mass_exact_at_q_n_plus_2(oracle_mod, N):
+    """eps = 1: the mass coupling is detJ, a polynomial of degree <= 5 per
+    axis on a triquadratic map, so the Gauss rule is exact once
+    2Q-1 >= 2(N-1)+5; all higher Q give the same discrete matrix."""
+    nodes = curved_nodes(11, 0.1)
+    (a,) = run_fill(oracle_mod, SCALAR, MAT_SINCOSEXP, nodes, [0.0], N, N + 2, 0.0, 1.0)
+    (b,) = run_fill(oracle_mod, SCALAR, MAT_SINCOSEXP, nodes, [0.0], N, 30, 0.0, 1.0)
+    assert np.abs(a - b).max() / np.abs(b).max() < 2e-14
+    (c,) = run_fill(oracle_mod, SCALAR, MAT_SINCOSEXP, nodes, [0.0], N, N + 1, 0.0, 1.0)
+    assert np.abs(c - b).max() / np.abs(b).max() > 1e-9  # below exactness it differs
+
+
+# ---------------------------------------------------------------- E2
+def _leg_series(m, kind):
+    c = np.zeros(m + 1)
+    if kind == "phi":
+        if m == 0:
+            return np.array([0.5, -0.5])
+        if m == 1:
+            return np.array([0.5, 0.5])
+        c[m] = 1.0
+        c[m - 2] = -1.0
+        return c / math.sqrt(2 * (2 * m - 1))
+    if kind == "dphi":
+        if m == 0:
+            return np.array([-0.5])
+        if m == 1:
+            return np.array([0.5])
+        return npleg.legder(_leg_series(m, "phi"))
+    if kind == "psi":
+        c[m] = math.sqrt((2 * m + 1) / 2)
+        return c
+
+
+def _exact_1d(s1, s2, power):
+    """exact integral over [-1,1] of (Legendre series s1)(s2) t^power."""
+    prod = npleg.legmul(npleg.legmul(s1, s2), npleg.poly2leg(np.eye(power + 1)[power]))
+    integ = npleg.legint(prod)
+    return npleg.legval(1.0, integ) - npleg.legval(-1.0, integ)
+
+
+@pytest.mark.parametrize("field,powers,Q", [(0, (2, 1, 0), (7, 7, 7)), (4, (1, 0, 3), (7, 7, 7)),
+                                            (6, (3, 2, 1), (7, 7, 7)), (1, (0, 2, 5), (5, 6, 8)),
+                                            (6, (1, 3, 0), (6, 8, 5))])
+def test_scalar_polynomial_alpha_exact(oracle_mod, field, powers, Q):
+    """Sampled coupling alpha = u^a v^b w^c in one field: the matrix is a
+    product of exact 1-D integrals (numpy Legendre series arithmetic).
+    Unequal rules per axis check that each axis uses its own weights."""
+    N = 4
+    a, b, c = powers
+    xs = [npleg.leggauss(q)[0] for q in Q]
+    U, V, Wc = np.meshgrid(*xs, indexing="ij")
+    F = 7
+    alpha = np.zeros((F, int(np.prod(Q))))
+    alpha[field] = (U ** a * V ** b * Wc ** c).reshape(-1)
+    (A,) = run_fill(oracle_mod, SCALAR, ALPHA_SAMPLED, nominal_nodes(), alpha.reshape(1, -1), N, Q)
+    # field -> (test derivative axis, trial derivative axis) or mass
+    pairs = {0: (0, 0), 1: (1, 1), 2: (2, 2), 3: (0, 1), 4: (0, 2), 5: (1, 2)}
+    ref = np.zeros_like(A)
+    terms = [pairs[field]] if field < 6 else [None]
+    if field in (3, 4, 5):
+        terms.append(pairs[field][::-1])
+    for t in terms:
+        mats = []
+        for ax, pw in enumerate((a, b, c)):
+            ka = "dphi" if (t is not None and t[0] == ax) else "phi"
+            kb = "dphi" if (t is not None and t[1] == ax) else "phi"
+            mats.append(np.array([[_exact_1d(_leg_series(m, ka), _leg_series(n, kb), pw)
+                                   for n in range(N)] for m in range(N)]))
+        ref += np.kron(np.kron(mats[0], mats[1]), mats[2])
+    assert np.abs(A - ref).max() < 1e-14
+
+
+# ---------------------------------------------------------------- moments
+def test_moments_of_legendre_alpha(oracle_mod):
+    """alpha = L_a(u) L_b(v) L_c(w): by orthogonality the moment tensor is a
+    single spike 8/((2a+1)(2b+1)(2c+1)) at (a,b,c)."""
+    Q, K = (8, 6, 9), 7
+    xs = [npleg.leggauss(q)[0] for q in Q]
+    U, V, Wc = np.meshgrid(*xs, indexing="ij")
+    a, b, c = 3, 0, 5
+    e = lambda n, t: npleg.legval(t, np.eye(n + 1)[n])
+    alpha = np.zeros((7, int(np.prod(Q))))
+    alpha[2] = (e(a, U) * e(b, V) * e(c, Wc)).reshape(-1)
+    I = oracle_mod.moments(SCALAR, ALPHA_SAMPLED, alpha, nominal_nodes(), *Q, K)
+    ref = np.zeros_like(I)
+    ref[2, a, b, c] = 8.0 / ((2 * a + 1) * (2 * b + 1) * (2 * c + 1))
+    assert np.abs(I - ref).max() < 1e-14
+
+
+# ---------------------------------------------------------------- B1
+def _lag1(t):
+    nodes = (-1.0, 0.0, 1.0)
+    out = []
+    for i, ti in enumerate(nodes):
+        v = 1.0
+        for j, tj in enumerate(nodes):
+            if j != i:
+                v = v * (t - tj) / (ti - tj)
+        out.append(v)
+    return out
+
+
+def _xmap(nodes, u):
+    lu, lv, lw = _lag1(u[0]), _lag1(u[1]), _lag1(u[2])
+    x = 0
+    for k in range(3):
+        for j in range(3):
+            for i in range(3):
+                x = x + lu[i] * lv[j] * lw[k] * nodes[i + 3 * j + 9 * k]
+    return x
+
+
+def _cstep(f, u, c, h=1e-30):
+    du = np.zeros(3, dtype=complex)
+    du[c] = 1j * h
+    return np.imag(f(u + du)) / h
+
+
+def _basis_fun(problem, N):
+    """List of callables u -> value (scalar) or E_hat (3-vector), built from
+    numpy Legendre series (independent of the oracle's evaluation)."""
+    fs = []
+    ser = lambda kind, m: _leg_series(m, kind)
+    if problem == SCALAR:
+        for m in range(N):
+            for n in range(N):
+                for p in range(N):
+                    s = (ser("phi", m), ser("phi", n), ser("phi", p))
+                    fs.append(lambda u, s=s: npleg.legval(u[0], s[0]) * npleg.legval(u[1], s[1]) * npleg.legval(u[2], s[2]))
+        return fs
+    for g in range(3):
+        dims = [N, N, N]
+        dims[g] = N - 1
+        for m in range(dims[0]):
+            for n in range(dims[1]):
+                for p in range(dims[2]):
+                    idx = (m, n, p)
+                    s = tuple(ser("psi" if ax == g else "phi", idx[ax]) for ax in range(3))
+
+                    def f(u, s=s, g=g):
+                        v = npleg.legval(u[0], s[0]) * npleg.legval(u[1], s[1]) * npleg.legval(u[2], s[2])
+                        e = np.zeros(3, dtype=complex)
+                        e = e + 0 * v
+                        e[g] = v
+                        return e
+                    fs.append(f)
+    return fs
+
+
+@pytest.mark.parametrize("problem,N", [(SCALAR, 2), (SCALAR, 3), (VECTOR, 2), (VECTOR, 3)])
+def test_brute_force_physical_space(oracle_mod, problem, N):
+    """Independent evaluation on one curved inhomogeneous element: the
+    physical gradient / curl is formed by the chain rule from complex-step
+    derivatives with respect to (u,v,w) of the pushed-forward fields
+    (scalar: phi; vector: E = J^{-T} E_hat), not from the Piola identity."""
+    nodes = curved_nodes(21, 0.1)
+    Q = 4
+    if problem == SCALAR:
+        material, mp = MAT_SINCOSEXP, np.array([2 * math.pi])
+    else:
+        rng = np.random.default_rng(9)
+        R, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+        material, mp = MAT_ROTDIAG, np.concatenate([R.reshape(-1), rng.standard_normal(3) * 3])
+    (A,) = run_fill(oracle_mod, problem, material, nodes, mp, N, Q)
+    x, w = npleg.leggauss(Q)
+    fs = _basis_fun(problem, N)
+    nd = len(fs)
+    ref = np.zeros((nd, nd))
+    for a in range(Q):
+        for b in range(Q):
+            for c in range(Q):
+                u = np.array([x[a], x[b], x[c]], dtype=complex)
+                W = w[a] * w[b] * w[c]
+                J = np.stack([_cstep(lambda t: _xmap(nodes, t), u, cc) for cc in range(3)], 1)
+                detJ = np.linalg.det(J)
+                Jinv = np.linalg.inv(J)
+                xp = np.real(_xmap(nodes, u))
+                eps = oracle_mod.permittivity(material, mp, xp)
+                if problem == SCALAR:
+                    vals = np.array([np.real(f(u)) for f in fs])
+                    gu = np.array([[_cstep(f, u, cc) for cc in range(3)] for f in fs])
+                    gx = gu @ Jinv  # d/dx_s = sum_c d/du_c (J^-1)_{c s}
+                    ref += W * detJ * (gx @ eps @ gx.T + eps[0, 0] * np.outer(vals, vals))
+                else:
+                    def pushed(f):
+                        def E(t):
+                            return np.linalg.solve(_jac_analytic(nodes, t).T, f(t))
+                        return E
+                    Ev = []
+                    Cv = []
+                    for f in fs:
+                        Ef = pushed(f)
+                        Ev.append(np.real(Ef(u)))
+                        dEdu = np.stack([_cstep_vec(Ef, u, cc) for cc in range(3)], 1)  # [r][c]
+                        dEdx = dEdu @ Jinv  # [r][s] = dE_r/dx_s
+                        Cv.append(np.array([dEdx[2, 1] - dEdx[1, 2], dEdx[0, 2] - dEdx[2, 0],
+                                            dEdx[1, 0] - dEdx[0, 1]]))
+                    Ev = np.array(Ev)
+                    Cv = np.array(Cv)
+                    ref += W * detJ * (Cv @ Cv.T + Ev @ eps @ Ev.T)
+    assert np.abs(A - ref).max() / np.abs(ref).max() < 1e-12
+
+
+def _dlag1(t):
+    """Derivatives of the quadratic Lagrange basis on {-1,0,1} by the generic
+    product rule (valid for complex t)."""
+    nodes = (-1.0, 0.0, 1.0)
+    out = []
+    for i, ti in enumerate(nodes):
+        s = 0.0
+        for m, tm in enumerate(nodes):
+            if m == i:
+                continue
+            p = 1.0 / (ti - tm)
+            for j, tj in enumerate(nodes):
+                if j != i and j != m:
+                    p = p * (t - tj) / (ti - tj)
+            s = s + p
+        out.append(s)
+    return out
+
+
+def _jac_analytic(nodes, u):
+    """J[r][c] = dx_r/du_c of the polynomial map at a (possibly complex) point."""
+    l = [_lag1(u[0]), _lag1(u[1]), _lag1(u[2])]
+    d = [_dlag1(u[0]), _dlag1(u[1]), _dlag1(u[2])]
+    J = np.zeros((3, 3), dtype=complex)
+    for k in range(3):
+        for j in range(3):
+            for i in range(3):
+                X = nodes[i + 3 * j + 9 * k]
+                J[:, 0] += d[0][i] * l[1][j] * l[2][k] * X
+                J[:, 1] += l[0][i] * d[1][j] * l[2][k] * X
+                J[:, 2] += l[0][i] * l[1][j] * d[2][k] * X
+    return J
+
+
+def _cstep_vec(f, u, c, h=1e-30):
+    du = np.zeros(3, dtype=complex)
+    du[c] = 1j * h
+    return np.imag(f(u + du)) / h
+
+
+# ---------------------------------------------------------------- S1
+@pytest.mark.parametrize("problem", [SCALAR, VECTOR])
+def test_symmetry(oracle_mod, problem):
+    from paper_1703_09619_amd import workloads as W
+    name = "scalar_n4" if problem == SCALAR else "vector_n6"
+    w = W.subset(W.make(name, E=64 if problem == SCALAR else 8), [0, 1, 2])
+    N = 4 if problem == SCALAR else 3
+    mats = run_fill(oracle_mod, problem, w.material, w.nodes, w.mat, N, 6)
+    for A in mats:
+        assert np.abs(A - A.T).max() <= 1e-15 * np.abs(A).max() * 10
+
+
+# ---------------------------------------------------------------- V1 / V2
+def _discrete_gradient(N):
+    D = _grad1(N)
+    I = np.eye(N)
+    return np.vstack([np.kron(np.kron(D, I), I), np.kron(np.kron(I, D), I),
+                      np.kron(np.kron(I, I), D)])
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_exact_sequence_curl_of_gradient(oracle_mod, N):
+    """curl grad = 0: the curl-curl matrix annihilates the discrete gradients
+    of the scalar space, for any geometry and material; its null space has
+    dimension N^3 - 1 (gradients modulo constants)."""
+    rng = np.random.default_rng(2)
+    R, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    mp = np.concatenate([R.reshape(-1), [3.0, -1.0, 2.0]])
+    (S,) = run_fill(oracle_mod, VECTOR, MAT_ROTDIAG, curved_nodes(4, 0.1), mp, N, N + 2, 1.0, 0.0)
+    G = _discrete_gradient(N)
+    assert np.abs(S @ G).max() < 1e-13 * np.abs(S).max()
+    ev = np.linalg.eigvalsh(S)
+    null = (np.abs(ev) < 1e-10 * ev.max()).sum()
+    assert null == N ** 3 - 1
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_vector_mass_on_gradients_is_scalar_stiffness(oracle_mod, N):
+    """E = grad(phi) turns the vector mass form into the scalar stiffness
+    form with the same permittivity: G^T M_vec G = K_scalar."""
+    nodes = curved_nodes(8, 0.1)
+    mp = [math.pi * 1.7]
+    (Mv,) = run_fill(oracle_mod, VECTOR, MAT_SINCOSEXP, nodes, mp, N, 5, 0.0, 1.0)
+    (Ks,) = run_fill(oracle_mod, SCALAR, MAT_SINCOSEXP, nodes, mp, N, 5, 1.0, 0.0)
+    G = _discrete_gradient(N)
+    assert np.abs(G.T @ Mv @ G - Ks).max() < 1e-14 * np.abs(Ks).max() * 10
+
+
+# ---------------------------------------------------------------- I1
+def test_translation_invariance(oracle_mod):
+    nodes = curved_nodes(30, 0.1)
+    k = np.array([2.0, -1.0, 3.0])
+    t = np.array([0.3, -0.7, 1.1])
+    mp = np.concatenate([k, [0.4]])
+    mp_shift = np.concatenate([k, [0.4 - k @ t]])
+    (A,) = run_fill(oracle_mod, SCALAR, MAT_PLANEWAVE, nodes, mp, 3, 6)
+    (B,) = run_fill(oracle_mod, SCALAR, MAT_PLANEWAVE, nodes + t, mp_shift, 3, 6)
+    assert np.abs(A - B).max() < 1e-13 * np.abs(A).max()
+
+
+def test_rotation_invariance_vector(oracle_mod):
+    rng = np.random.default_rng(77)
+    nodes = curved_nodes(31, 0.1)
+    R, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    Rr, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    k = rng.standard_normal(3) * 4
+    mp = np.concatenate([R.reshape(-1), k])
+    mp_rot = np.concatenate([(R @ Rr.T).reshape(-1), Rr @ k])
+    (A,) = run_fill(oracle_mod, VECTOR, MAT_ROTDIAG, nodes, mp, 3, 5)
+    (B,) = run_fill(oracle_mod, VECTOR, MAT_ROTDIAG, nodes @ Rr.T, mp_rot, 3, 5)
+    assert np.abs(A - B).max() < 1e-13 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("problem", [SCALAR, VECTOR])
+def test_scaling(oracle_mod, problem):
+    """x -> h x with constant eps: scalar stiffness ~ h, scalar mass ~ h^3;
+    vector curl-curl ~ 1/h, vector mass ~ h."""
+    nodes = curved_nodes(40, 0.1)
+    h = 2.5
+    N = 3
+    sK = lambda nd: run_fill(oracle_mod, problem, MAT_SINCOSEXP, nd, [0.0], N, 5, 1.0, 0.0)[0]
+    sM = lambda nd: run_fill(oracle_mod, problem, MAT_SINCOSEXP, nd, [0.0], N, 5, 0.0, 1.0)[0]
+    if problem == SCALAR:
+        fk, fm = h, h ** 3
+    else:
+        fk, fm = 1 / h, h
+    A, B = sK(nodes), sK(h * nodes)
+    assert np.abs(B - fk * A).max() < 1e-13 * np.abs(B).max()
+    A, B = sM(nodes), sM(h * nodes)
+    assert np.abs(B - fm * A).max() < 1e-13 * np.abs(B).max()
+
+
+def test_inverted_element_sets_status(oracle_mod):
+    nodes = nominal_nodes().copy()
+    nodes[13] = (2.0, 2.0, 2.0)  # centre node far outside: tangled map
+    out, off, st = oracle_mod.fill(SCALAR, MAT_SINCOSEXP, nodes[None], np.array([[1.0]]),
+                                   np.array([3], np.int32), np.array([[4, 4, 4]], np.int32))
+    assert st[0] & 1
