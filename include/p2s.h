@@ -1,0 +1,186 @@
+/*
+ * p2s.h -- C ABI of the product-to-sum element-matrix fill for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The library fills dense element matrices of a hierarchical finite-element
+ * method on curved, inhomogeneous hexahedra (eq. (2) of Khodapanah, "A
+ * Product to Sum Approach for Matrix Filling in a Hierarchical Finite-Element
+ * Method", Section II) with the product-to-sum method:
+ *   (a) moments:  I_s[k,l,q] = int int int L_k(u) L_l(v) L_q(w) alpha_s du dv dw
+ *       by tensor Gauss quadrature of the sampled coupling factor alpha_s
+ *       (the 3-D integrals of eq. (4));
+ *   (b) tables:   every same-variable product of two 1-D basis/weighting
+ *       functions is expanded in Legendre polynomials (eq. (3)), with
+ *       coefficients tabulated once per context;
+ *   (c) contraction: M = sum_s sum_{k,l,q} Cu Cv Cw I_s (eq. (4)), applied
+ *       mode by mode.
+ *
+ * Instance of the paper's general form (Section II, eq. (1)):
+ *   reference cube [-1,1]^3; triquadratic 27-node isoparametric map;
+ *   integrated-Legendre basis phi_0=(1-t)/2, phi_1=(1+t)/2,
+ *   phi_m=(L_m-L_{m-2})/sqrt(2(2m-1)); vector components use
+ *   psi_m=sqrt((2m+1)/2) L_m along their own axis (orders (N-1,N,N),
+ *   (N,N-1,N), (N,N,N-1), the 3-D analogue of eq. (6)).
+ *
+ *   P2S_SCALAR: stiff_scale * int eps grad(u).grad(v)
+ *             + mass_scale  * int eps u v             (N^3 dofs)
+ *   P2S_VECTOR: stiff_scale * int curl(E).curl(F)      (mu = 1)
+ *             + mass_scale  * int E.eps F             (3 (N-1) N^2 dofs)
+ *
+ * Memory and ownership.  Pointers marked [device] are device memory on the
+ * context's GPU, owned by the caller; [host] are host memory owned by the
+ * caller.  The library owns its tables, plans and workspaces.  Calls that
+ * take a stream enqueue work asynchronously on that HIP stream (NULL = the
+ * default stream) and return after enqueueing; argument errors are detected
+ * before anything is enqueued.  Execution calls allocate nothing.
+ *
+ * Errors.  Every int-returning call returns P2S_OK (0) or a negative
+ * p2s_status; p2s_last_error() returns a message for the last failure on
+ * that context.  Per-element numerical conditions are reported in the
+ * status array, never in the return code.
+ *
+ * Thread safety.  A context may be used from one host thread at a time.
+ */
+#ifndef P2S_H
+#define P2S_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct p2s_ctx_s *p2s_ctx;
+typedef struct p2s_plan_s *p2s_plan;
+
+typedef enum {
+    P2S_OK = 0,
+    P2S_EINVAL = -1,   /* bad argument (null pointer, size, enum)          */
+    P2S_EORDER = -2,   /* polynomial order outside [2, P2S_MAX_ORDER]       */
+    P2S_EQUAD = -3,    /* Gauss points per axis outside [1, P2S_MAX_Q]      */
+    P2S_ENOMEM = -4,   /* device or host allocation failed (plan creation)  */
+    P2S_EHIP = -5,     /* a HIP runtime call failed                         */
+    P2S_ENODEV = -6,   /* no usable gfx950 device                           */
+    P2S_ENOMODEL = -7  /* learned-order call without a loaded model         */
+} p2s_status;
+
+typedef enum { P2S_SCALAR = 0, P2S_VECTOR = 1 } p2s_problem;
+
+/* Material models; material parameters per element, [E][P]:
+ *  SINCOSEXP  P=1  eps = 1 + 0.5 sin(kappa x) cos(kappa y) exp(-z)  {kappa}
+ *  ROTDIAG    P=12 eps = R^T diag(d) R, d_a = 1 + 0.5 sin(k.x + 2 pi a/3)
+ *                  {R row-major (9), k (3)}                (vector only)
+ *  PLANEWAVE  P=4  eps = 1 + 0.8 sin(k.x + phase)     {k (3), phase}
+ *  ALPHA_SAMPLED   the coupling fields themselves at the Gauss points,
+ *                  [E][F][Qu*Qv*Qw], point (a*Qv+b)*Qw+c (a along u),
+ *                  F = 7 scalar (A00 A11 A22 A01 A02 A12 mass) or
+ *                  12 vector (C00 C11 C22 C01 C02 C12 M00 M11 M22 M01 M02 M12);
+ *                  all elements must share one rule; nodes are ignored.
+ * Isotropic materials act as eps*I in the vector problem. */
+typedef enum {
+    P2S_MAT_SINCOSEXP = 0,
+    P2S_MAT_ROTDIAG = 1,
+    P2S_MAT_PLANEWAVE = 2,
+    P2S_ALPHA_SAMPLED = 3
+} p2s_material;
+
+/* Arithmetic of stages (a) and (c).  FP64 throughout, or the split-FP32
+ * form: moments and contraction on FP32 matrix cores with each operand
+ * split into two FP32 parts, map/Jacobian/coupling/tables/final
+ * accumulation in FP64. */
+typedef enum { P2S_FP64 = 0, P2S_SPLIT_FP32 = 1 } p2s_precision;
+
+/* Method: product-to-sum (the paper's method) or direct quadrature of
+ * eq. (2) on the GPU (the baseline the paper compares against). */
+typedef enum { P2S_METHOD_P2S = 0, P2S_METHOD_DIRECT = 1 } p2s_method;
+
+typedef struct {
+    int32_t problem;     /* p2s_problem                      */
+    int32_t material;    /* p2s_material                     */
+    int32_t precision;   /* p2s_precision                    */
+    int32_t method;      /* p2s_method                       */
+    double stiff_scale;  /* weight of the stiffness term (1) */
+    double mass_scale;   /* weight of the mass term (1)      */
+} p2s_terms;
+
+#define P2S_MAX_ORDER 8
+#define P2S_MAX_Q 32
+
+/* per-element status bits */
+#define P2S_STATUS_DETJ 1u      /* det J <= 0 at some Gauss point          */
+#define P2S_STATUS_NONFINITE 2u /* non-finite value in the element matrix */
+#define P2S_STATUS_FALLBACK 4u  /* learned order rejected, refilled at max */
+#define P2S_STATUS_TAIL 8u      /* tail check still above tolerance        */
+
+/* Create a context on HIP device `device`: checks that it is gfx950,
+ * builds the FP64 tables (Gauss rules up to P2S_MAX_Q points, Legendre
+ * linearization of every basis-pair family up to P2S_MAX_ORDER) once on the
+ * host and uploads them.  *out receives the handle. */
+int p2s_create(p2s_ctx *out, int device);
+void p2s_destroy(p2s_ctx ctx);
+/* Message of the last failure on ctx (or of the last p2s_create failure
+ * when ctx is NULL).  Valid until the next call on ctx. */
+const char *p2s_last_error(p2s_ctx ctx);
+
+/* Degrees of freedom of one element of order N (N^3 or 3 (N-1) N^2);
+ * -1 for a bad problem or order. */
+int64_t p2s_num_dofs(int problem, int N);
+
+/* Output layout: offsets[e] is the start (in doubles) of element e's dense
+ * row-major block, offsets[E] the total.  orders [host][E],
+ * offsets [host][E+1]. */
+int p2s_layout(int problem, int64_t E, const int32_t *orders, int64_t *offsets);
+
+/* Plan: the schedule, per-element descriptors and workspace for one batch
+ * shape (E, orders [host][E], quad [host][E][3] Gauss points per axis).
+ * Allocates device memory; execution then allocates nothing. */
+int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E,
+                    const int32_t *orders, const int32_t *quad, p2s_plan *out);
+/* Enqueue the fill on `stream`:
+ *  nodes    [device] [E][27][3]  node (i,j,k) at i+3j+9k, i along u
+ *  material [device] per p2s_material
+ *  out      [device] concatenated dense row-major FP64 blocks, p2s_layout
+ *  status   [device] [E] per-element P2S_STATUS_* bits (overwritten)   */
+int p2s_plan_execute(p2s_plan plan, const double *nodes, const double *material,
+                     double *out, uint32_t *status, void *stream);
+/* Bytes of device workspace held by the plan. */
+int64_t p2s_plan_workspace_bytes(p2s_plan plan);
+void p2s_plan_destroy(p2s_plan plan);
+
+/* Stage timing.  With enable != 0, every later p2s_plan_execute records HIP
+ * events on its stream around each stage launch (0 coupling, 1 moments,
+ * 2 contraction, 3 other); p2s_plan_profile_read waits for those events and
+ * returns, per stage, the summed milliseconds and the launch count since the
+ * last read (then resets).  ms [host][4], launches [host][4]. */
+int p2s_plan_profile(p2s_plan plan, int enable);
+int p2s_plan_profile_read(p2s_plan plan, double *ms, int64_t *launches);
+
+/* One-shot fill: plan create + execute + destroy (the plan is destroyed
+ * after the stream has finished the work, so this call synchronizes the
+ * stream).  Arguments as above. */
+int p2s_fill_element_matrices(p2s_ctx ctx, const p2s_terms *terms, int64_t E,
+                              const double *nodes, const double *material,
+                              const int32_t *orders, const int32_t *quad,
+                              double *out, uint32_t *status, void *stream);
+
+/* Stage outputs, for verification of each step against its definition.
+ * Coupling samples: alpha [device][E][F][Qu*Qv*Qw] (unweighted, packed
+ * field order of P2S_ALPHA_SAMPLED).  Moments: [device][E][F][K][K][K],
+ * K = 2N-1, the integrals of eq. (4).  Both need a plan of uniform shape. */
+int p2s_plan_coupling(p2s_plan plan, const double *nodes, const double *material,
+                      double *alpha, void *stream);
+int p2s_plan_moments(p2s_plan plan, const double *nodes, const double *material,
+                     double *moments, void *stream);
+
+/* Host-side tables (no device needed).
+ * Gauss-Legendre rule with Q points, ascending: x[Q], w[Q].
+ * Linearization (eq. (3)): X_m1(t) Y_m2(t) = sum_k coef[k] L_k(t),
+ * families 0 = phi, 1 = phi', 2 = psi; coef[2*P2S_MAX_ORDER]. */
+int p2s_gauss_rule(int Q, double *x, double *w);
+int p2s_linearization(int xfam, int m1, int yfam, int m2, double *coef);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P2S_H */

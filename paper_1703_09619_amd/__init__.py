@@ -1,0 +1,253 @@
+"""Product-to-sum element-matrix fill on AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding of the C ABI in include/p2s.h (argument marshalling
+only; every stage of the fill runs in the HIP kernels of libp2s.so).
+PyTorch supplies device memory and the stream.
+
+    import torch, paper_1703_09619_amd as p2s
+    ctx = p2s.Context(0)
+    plan = ctx.plan(p2s.VECTOR, p2s.MAT_ROTDIAG, orders, quad)
+    out, status = plan.execute(nodes_dev, material_dev)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libp2s.so")
+
+SCALAR, VECTOR = 0, 1
+MAT_SINCOSEXP, MAT_ROTDIAG, MAT_PLANEWAVE, ALPHA_SAMPLED = 0, 1, 2, 3
+FP64, SPLIT_FP32 = 0, 1
+METHOD_P2S, METHOD_DIRECT = 0, 1
+FAM_PHI, FAM_DPHI, FAM_PSI = 0, 1, 2
+STATUS_DETJ, STATUS_NONFINITE, STATUS_FALLBACK, STATUS_TAIL = 1, 2, 4, 8
+MAX_ORDER, MAX_Q = 8, 32
+
+# every symbol the C ABI exports (include/p2s.h)
+EXPORTS = (
+    "p2s_create", "p2s_destroy", "p2s_last_error", "p2s_num_dofs", "p2s_layout",
+    "p2s_plan_create", "p2s_plan_execute", "p2s_plan_workspace_bytes", "p2s_plan_destroy",
+    "p2s_fill_element_matrices", "p2s_plan_coupling", "p2s_plan_moments",
+    "p2s_gauss_rule", "p2s_linearization", "p2s_plan_profile", "p2s_plan_profile_read",
+)
+
+
+class P2SError(RuntimeError):
+    pass
+
+
+class _Terms(ctypes.Structure):
+    _fields_ = [("problem", ctypes.c_int32), ("material", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("stiff_scale", ctypes.c_double), ("mass_scale", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libp2s.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise P2SError("libp2s.so is not built: run `python -m paper_1703_09619_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        lib.p2s_create.argtypes = [ctypes.POINTER(vp), i32]
+        lib.p2s_destroy.argtypes = [vp]
+        lib.p2s_destroy.restype = None
+        lib.p2s_last_error.argtypes = [vp]
+        lib.p2s_last_error.restype = ctypes.c_char_p
+        lib.p2s_num_dofs.argtypes = [i32, i32]
+        lib.p2s_num_dofs.restype = i64
+        lib.p2s_layout.argtypes = [i32, i64, vp, vp]
+        lib.p2s_plan_create.argtypes = [vp, ctypes.POINTER(_Terms), i64, vp, vp, ctypes.POINTER(vp)]
+        lib.p2s_plan_execute.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.p2s_plan_workspace_bytes.argtypes = [vp]
+        lib.p2s_plan_workspace_bytes.restype = i64
+        lib.p2s_plan_destroy.argtypes = [vp]
+        lib.p2s_plan_destroy.restype = None
+        lib.p2s_fill_element_matrices.argtypes = [vp, ctypes.POINTER(_Terms), i64, vp, vp, vp, vp, vp, vp, vp]
+        lib.p2s_plan_coupling.argtypes = [vp, vp, vp, vp, vp]
+        lib.p2s_plan_moments.argtypes = [vp, vp, vp, vp, vp]
+        lib.p2s_plan_profile.argtypes = [vp, i32]
+        lib.p2s_plan_profile_read.argtypes = [vp, vp, vp]
+        lib.p2s_gauss_rule.argtypes = [i32, vp, vp]
+        lib.p2s_linearization.argtypes = [i32, i32, i32, i32, vp]
+        for f in ("p2s_create", "p2s_layout", "p2s_plan_create", "p2s_plan_execute",
+                  "p2s_fill_element_matrices", "p2s_plan_coupling", "p2s_plan_moments",
+                  "p2s_gauss_rule", "p2s_linearization", "p2s_plan_profile", "p2s_plan_profile_read"):
+            getattr(lib, f).restype = i32
+        _lib = lib
+    return _lib
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev_ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def num_dofs(problem: int, N: int) -> int:
+    return int(load().p2s_num_dofs(problem, N))
+
+
+def layout(problem: int, orders) -> np.ndarray:
+    orders = np.ascontiguousarray(orders, dtype=np.int32)
+    off = np.zeros(len(orders) + 1, dtype=np.int64)
+    rc = load().p2s_layout(problem, len(orders), _np_ptr(orders), _np_ptr(off))
+    if rc != 0:
+        raise P2SError("p2s_layout failed: %d" % rc)
+    return off
+
+
+def gauss_rule(Q: int):
+    x = np.zeros(Q)
+    w = np.zeros(Q)
+    rc = load().p2s_gauss_rule(Q, _np_ptr(x), _np_ptr(w))
+    if rc != 0:
+        raise P2SError("p2s_gauss_rule failed: %d" % rc)
+    return x, w
+
+
+def linearization(xfam: int, m1: int, yfam: int, m2: int) -> np.ndarray:
+    c = np.zeros(2 * MAX_ORDER)
+    rc = load().p2s_linearization(xfam, m1, yfam, m2, _np_ptr(c))
+    if rc != 0:
+        raise P2SError("p2s_linearization failed: %d" % rc)
+    return c
+
+
+def terms(problem: int, material: int, precision: int = FP64, method: int = METHOD_P2S,
+          stiff_scale: float = 1.0, mass_scale: float = 1.0) -> _Terms:
+    return _Terms(problem, material, precision, method, stiff_scale, mass_scale)
+
+
+class Context:
+    """A library context on one GPU (tables built once)."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        rc = lib.p2s_create(ctypes.byref(h), device)
+        if rc != 0:
+            raise P2SError("p2s_create failed (%d): %s" % (rc, lib.p2s_last_error(None).decode()))
+        self._h = h
+        self.device = device
+
+    def error(self) -> str:
+        return load().p2s_last_error(self._h).decode()
+
+    def check(self, rc: int, what: str):
+        if rc != 0:
+            raise P2SError("%s failed (%d): %s" % (what, rc, self.error()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().p2s_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def plan(self, problem, material, orders, quad, precision=FP64, method=METHOD_P2S,
+             stiff_scale=1.0, mass_scale=1.0) -> "Plan":
+        return Plan(self, terms(problem, material, precision, method, stiff_scale, mass_scale), orders, quad)
+
+
+class Plan:
+    """Schedule + workspace for one batch shape; execute() allocates nothing
+    in the library (the output tensors are allocated by torch unless given)."""
+
+    def __init__(self, ctx: Context, t: _Terms, orders, quad):
+        self.ctx = ctx
+        self.terms = t
+        self.orders = np.ascontiguousarray(orders, dtype=np.int32)
+        self.quad = np.ascontiguousarray(quad, dtype=np.int32).reshape(-1, 3)
+        self.E = len(self.orders)
+        h = ctypes.c_void_p()
+        rc = load().p2s_plan_create(ctx._h, ctypes.byref(t), self.E, _np_ptr(self.orders),
+                                    _np_ptr(self.quad), ctypes.byref(h))
+        ctx.check(rc, "p2s_plan_create")
+        self._h = h
+        self.offsets = layout(t.problem, self.orders) if self.E else np.zeros(1, np.int64)
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(load().p2s_plan_workspace_bytes(self._h))
+
+    def execute(self, nodes, material, out=None, status=None, stream=None):
+        import torch
+        dev = torch.device("cuda", self.ctx.device)
+        if out is None:
+            out = torch.empty(int(self.offsets[-1]), dtype=torch.float64, device=dev)
+        if status is None:
+            status = torch.empty(self.E, dtype=torch.int32, device=dev)
+        rc = load().p2s_plan_execute(self._h, _dev_ptr(nodes), _dev_ptr(material), _dev_ptr(out),
+                                     _dev_ptr(status), _stream(stream))
+        self.ctx.check(rc, "p2s_plan_execute")
+        return out, status
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around each stage launch of later executions."""
+        self.ctx.check(load().p2s_plan_profile(self._h, int(enable)), "p2s_plan_profile")
+
+    def profile_read(self):
+        """{stage: (ms, launches)} since the last read, stages coupling,
+        moments, contraction, other."""
+        ms = np.zeros(4)
+        n = np.zeros(4, dtype=np.int64)
+        self.ctx.check(load().p2s_plan_profile_read(self._h, _np_ptr(ms), _np_ptr(n)), "p2s_plan_profile_read")
+        names = ("coupling", "moments", "contraction", "other")
+        return {names[i]: (float(ms[i]), int(n[i])) for i in range(4)}
+
+    def coupling(self, nodes, material, stream=None):
+        import torch
+        F = 7 if self.terms.problem == SCALAR else 12
+        P = int(np.prod(self.quad[0])) if self.E else 0
+        a = torch.empty(self.E * F * P, dtype=torch.float64, device=torch.device("cuda", self.ctx.device))
+        rc = load().p2s_plan_coupling(self._h, _dev_ptr(nodes), _dev_ptr(material), _dev_ptr(a), _stream(stream))
+        self.ctx.check(rc, "p2s_plan_coupling")
+        return a.view(self.E, F, P)
+
+    def moments(self, nodes, material, stream=None):
+        import torch
+        F = 7 if self.terms.problem == SCALAR else 12
+        K = 2 * int(self.orders[0]) - 1 if self.E else 1
+        m = torch.empty(self.E * F * K ** 3, dtype=torch.float64, device=torch.device("cuda", self.ctx.device))
+        rc = load().p2s_plan_moments(self._h, _dev_ptr(nodes), _dev_ptr(material), _dev_ptr(m), _stream(stream))
+        self.ctx.check(rc, "p2s_plan_moments")
+        return m.view(self.E, F, K, K, K)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().p2s_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fill(ctx: Context, problem, material_kind, nodes, material, orders, quad, **kw):
+    """One-shot fill with device tensors; returns (out, offsets, status)."""
+    p = ctx.plan(problem, material_kind, orders, quad, **kw)
+    out, status = p.execute(nodes, material)
+    return out, p.offsets, status

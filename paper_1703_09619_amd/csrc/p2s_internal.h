@@ -1,0 +1,114 @@
+// p2s_internal.h -- layouts and compile-time structure shared by the host
+// runtime and the HIP kernels of the product-to-sum fill.
+#pragma once
+
+#include <stdint.h>
+
+#ifndef __HIPCC__
+#define P2S_HD
+#else
+#define P2S_HD __host__ __device__
+#endif
+
+namespace p2s {
+
+constexpr int MAXN = 8;          // largest order N (functions per direction)
+constexpr int KPAD = 16;         // padded Legendre-degree extent (K = 2N-1 <= 15)
+constexpr int MAXQ = 32;         // largest Gauss rule per axis
+constexpr int NFAM = 3;          // 1-D families: phi, phi', psi
+enum Fam : int { PHI = 0, DPHI = 1, PSI = 2 };
+
+// Linearization tables, eq. (3): lin[t][m1][m2][k] with type t = 3*X + Y
+// (X test family, Y trial family):  X_m1 Y_m2 = sum_k lin L_k.
+constexpr int NTYPE = NFAM * NFAM;
+constexpr int LIN_STRIDE_M1 = MAXN * KPAD;
+constexpr int LIN_STRIDE_T = MAXN * MAXN * KPAD;
+constexpr int LIN_SIZE = NTYPE * LIN_STRIDE_T;
+
+// Gauss tables for Q = 1..MAXQ: x[Q][a], w[Q][a], and the moment weights
+// legw[Q][k][a] = w_a L_k(x_a) for k < KPAD.
+constexpr int GX_SIZE = (MAXQ + 1) * MAXQ;
+constexpr int LEGW_STRIDE_Q = KPAD * MAXQ;
+constexpr int LEGW_SIZE = (MAXQ + 1) * LEGW_STRIDE_Q;
+
+// Offsets of the device table buffer (in doubles).
+constexpr int TAB_LIN = 0;
+constexpr int TAB_GX = TAB_LIN + LIN_SIZE;
+constexpr int TAB_GW = TAB_GX + GX_SIZE;
+constexpr int TAB_LEGW = TAB_GW + GX_SIZE;
+constexpr int TAB_SIZE = TAB_LEGW + LEGW_SIZE;
+
+P2S_HD constexpr int fam_dim(int fam, int N) { return fam == PSI ? N - 1 : N; }
+
+// Legendre degrees present in the expansion of family member m.
+P2S_HD constexpr uint32_t fam_support(int fam, int m)
+{
+    return fam == PHI ? (m < 2 ? 3u : ((1u << m) | (1u << (m - 2))))
+         : fam == DPHI ? (m < 2 ? 1u : (1u << (m - 1)))
+                       : (1u << m);
+}
+
+// Degrees k with a structurally nonzero lin[.][m1][m2][k]: the Legendre
+// product L_a L_b spans degrees |a-b|, |a-b|+2, ..., a+b.
+P2S_HD constexpr uint32_t prod_mask(int fx, int m1, int fy, int m2)
+{
+    uint32_t sx = fam_support(fx, m1), sy = fam_support(fy, m2), r = 0;
+    for (int a = 0; a < KPAD; ++a) {
+        if (!((sx >> a) & 1u)) continue;
+        for (int b = 0; b < KPAD; ++b) {
+            if (!((sy >> b) & 1u)) continue;
+            int lo = a > b ? a - b : b - a;
+            for (int k = lo; k <= a + b; k += 2) r |= 1u << k;
+        }
+    }
+    return r;
+}
+
+// One coupling term of a block (i,j): moment field, sign, and the family
+// pair (test, trial) on each axis.  Scale selects stiff_scale (0) or
+// mass_scale (1).
+struct Term {
+    int8_t field, sign, tu, tv, tw, scale;
+};
+
+constexpr int MAX_TERMS = 10;  // scalar: 9 stiffness + 1 mass; vector: 5 per block
+
+// Mirrors of the public enums and status bits (include/p2s.h).
+enum MatKind : int { MAT_SINCOSEXP = 0, MAT_ROTDIAG = 1, MAT_PLANEWAVE = 2, ALPHA_SAMPLED = 3 };
+constexpr uint32_t P2S_STATUS_DETJ_BIT = 1u;
+constexpr uint32_t P2S_STATUS_NONFINITE_BIT = 2u;
+constexpr uint32_t P2S_STATUS_FALLBACK_BIT = 4u;
+constexpr uint32_t P2S_STATUS_TAIL_BIT = 8u;
+
+// Per-element descriptor used by every kernel.
+struct ElemDesc {
+    int32_t N, Qu, Qv, Qw;
+    int64_t out_off;    // start of the element's block in out (doubles)
+    int64_t alpha_off;  // start of its coupling samples in the workspace
+    int64_t mom_off;    // start of its moment tensors in the workspace
+};
+
+// Problem shape helpers (host and device).
+P2S_HD constexpr int num_fields(int problem) { return problem == 0 ? 7 : 12; }
+P2S_HD constexpr int num_comp(int problem) { return problem == 0 ? 1 : 3; }
+// dimension of component g along axis ax
+P2S_HD constexpr int comp_dim(int problem, int N, int g, int ax)
+{
+    return (problem == 1 && g == ax) ? N - 1 : N;
+}
+P2S_HD constexpr int comp_size(int problem, int N, int g)
+{
+    return comp_dim(problem, N, g, 0) * comp_dim(problem, N, g, 1) * comp_dim(problem, N, g, 2);
+}
+P2S_HD constexpr int comp_offset(int problem, int N, int g)
+{
+    int o = 0;
+    for (int h = 0; h < g; ++h) o += comp_size(problem, N, h);
+    return o;
+}
+P2S_HD constexpr int num_dofs(int problem, int N)
+{
+    return comp_offset(problem, N, num_comp(problem));
+}
+
+}  // namespace p2s

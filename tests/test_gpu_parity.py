@@ -1,0 +1,232 @@
+"""GPU parity: the HIP product-to-sum fill against the CPU oracle (direct
+quadrature of eq. (2)) on the same seeded inputs, through the C ABI.
+
+Bar: per-element relative Frobenius error <= 1e-10 for the FP64 path.
+Both sides use the same tensor Gauss rule, and eq. (3) is an exact
+polynomial identity, so the two agree to rounding (the paper's claim that
+the method leaves accuracy unchanged, Section V)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    import paper_1703_09619_amd as p2s
+    from paper_1703_09619_amd import workloads as W
+    oracle.build(force=False)
+    ctx = p2s.Context(0)
+    return dict(torch=torch, oracle=oracle, p2s=p2s, W=W, ctx=ctx)
+
+
+def gpu_fill(env, w, **kw):
+    torch, p2s = env["torch"], env["p2s"]
+    plan = env["ctx"].plan(w["problem"], w["material"], w["orders"], w["quad"], **kw)
+    nodes = torch.from_numpy(np.ascontiguousarray(w["nodes"])).cuda()
+    mat = torch.from_numpy(np.ascontiguousarray(w["mat"])).cuda()
+    out, status = plan.execute(nodes, mat)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), plan.offsets, status.cpu().numpy(), plan
+
+
+def rel_errors(a, b, off):
+    errs = []
+    for e in range(len(off) - 1):
+        x, y = a[off[e]:off[e + 1]], b[off[e]:off[e + 1]]
+        errs.append(np.linalg.norm(x - y) / np.linalg.norm(y))
+    return np.array(errs)
+
+
+def check_against_oracle(env, w, sK=1.0, sM=1.0, tol=TOL):
+    print("case", w.get("name"), "E", w["E"], "orders", sorted(set(np.asarray(w["orders"]).tolist())),
+          "quad0", np.asarray(w["quad"])[0].tolist(), flush=True)
+    out, off, st, _ = gpu_fill(env, w, stiff_scale=sK, mass_scale=sM)
+    ref, roff, rst = env["oracle"].fill(w["problem"], w["material"], w["nodes"], w["mat"],
+                                        w["orders"], w["quad"], sK, sM)
+    assert np.array_equal(off, roff)
+    assert np.array_equal(st, rst.astype(st.dtype))
+    errs = rel_errors(out, ref, off)
+    print("max rel Frobenius error %.3e" % errs.max(), flush=True)
+    assert errs.max() <= tol
+    return errs
+
+
+def make_small(env, problem, N, E, Q, seed, material=None):
+    W = env["W"]
+    rng = np.random.default_rng(seed)
+    nodes, _, _ = W.perturbed_nodes(rng, E, 0.12)
+    if problem == W.SCALAR:
+        material = W.MAT_SINCOSEXP if material is None else material
+        if material == W.MAT_SINCOSEXP:
+            mat = rng.uniform(math.pi, 4 * math.pi, size=(E, 1))
+        else:
+            mat = np.concatenate([W.unit_vectors(rng, E) * 6.0, rng.uniform(0, 6, (E, 1))], 1)
+    else:
+        material = W.MAT_ROTDIAG
+        mat = np.zeros((E, 12))
+        for e in range(E):
+            mat[e, :9] = W.haar_rotation(rng).reshape(-1)
+        mat[:, 9:] = W.unit_vectors(rng, E) * rng.uniform(0, 4 * math.pi, (E, 1))
+    return W.Workload(name="small", problem=problem, material=material, E=E, nodes=nodes, mat=mat,
+                      orders=np.full(E, N, np.int32), quad=np.tile(np.array(Q, np.int32), (E, 1)))
+
+
+def test_scalar_n4_all_64_elements(env):
+    """The 64-element scalar workload (N=4, 8^3 points), every element."""
+    w = env["W"].make("scalar_n4")
+    check_against_oracle(env, w)
+
+
+def test_vector_n6_subset(env):
+    """Vector curl-curl + mass, N=6 (540 dofs), 12^3 points: a seeded
+    subset of the 4096-element workload."""
+    W = env["W"]
+    w = W.make("vector_n6", E=16)
+    check_against_oracle(env, W.subset(w, np.arange(6)))
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 7, 8])
+def test_scalar_orders_anisotropic_rule(env, N):
+    w = make_small(env, 0, N, 3, (N + 1, N + 2, N + 3), seed=100 + N)
+    check_against_oracle(env, w)
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 7, 8])
+def test_vector_orders_anisotropic_rule(env, N):
+    Q = (N + 2, N + 1, N + 3) if N < 7 else (5, 6, 7)
+    w = make_small(env, 1, N, 2, Q, seed=200 + N)
+    check_against_oracle(env, w)
+
+
+def test_planewave_material_and_scales(env):
+    w = make_small(env, 0, 5, 4, (9, 10, 11), seed=7, material=2)
+    check_against_oracle(env, w, sK=0.0, sM=1.0)
+    check_against_oracle(env, w, sK=1.0, sM=0.0)
+    check_against_oracle(env, w, sK=1.0, sM=-2.5)
+
+
+def test_vector_scales(env):
+    w = make_small(env, 1, 4, 3, (6, 6, 6), seed=8)
+    check_against_oracle(env, w, sK=1.0, sM=0.0)
+    check_against_oracle(env, w, sK=0.0, sM=1.0)
+
+
+def test_mixed_orders_batch(env):
+    """Elements of orders 2..8 in one plan (Q = 2N per element), ragged."""
+    W = env["W"]
+    w = W.make("scalar_mixed", E=200)
+    idx = []
+    for N in range(2, 9):
+        idx += list(np.nonzero(w["orders"] == N)[0][:2])
+    sub = W.subset(w, np.array(sorted(idx)))
+    check_against_oracle(env, sub)
+
+
+def test_sampled_coupling_input(env):
+    """Coupling fields given directly at the Gauss points (no geometry)."""
+    W = env["W"]
+    rng = np.random.default_rng(5)
+    for problem, F in ((0, 7), (1, 12)):
+        N, Q = 4, (5, 6, 7)
+        E = 3
+        a = rng.standard_normal((E, F, int(np.prod(Q))))
+        w = W.Workload(name="sampled", problem=problem, material=W.ALPHA_SAMPLED, E=E,
+                       nodes=np.zeros((E, 27, 3)), mat=a.reshape(E, -1),
+                       orders=np.full(E, N, np.int32), quad=np.tile(np.array(Q, np.int32), (E, 1)))
+        check_against_oracle(env, w)
+
+
+def test_coupling_stage(env):
+    """Stage (geometry + coupling factors) against the oracle's samples."""
+    torch, oracle, W = env["torch"], env["oracle"], env["W"]
+    for name, E in (("scalar_n4", 5), ("vector_n6", 3)):
+        w = W.subset(W.make(name, E=64 if name == "scalar_n4" else 8), np.arange(E))
+        plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
+        a = plan.coupling(torch.from_numpy(w.nodes).cuda(), torch.from_numpy(w.mat).cuda()).cpu().numpy()
+        for e in range(E):
+            ref = oracle.coupling(w.problem, w.material, w.mat[e], w.nodes[e], *w.quad[e])
+            assert np.abs(a[e] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_moment_stage(env):
+    """Stage (a): moments against their plain definition in the oracle."""
+    torch, oracle, W = env["torch"], env["oracle"], env["W"]
+    for name, E in (("scalar_n4", 4), ("vector_n6", 2)):
+        w = W.subset(W.make(name, E=64 if name == "scalar_n4" else 8), np.arange(E))
+        plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
+        m = plan.moments(torch.from_numpy(w.nodes).cuda(), torch.from_numpy(w.mat).cuda()).cpu().numpy()
+        K = 2 * int(w.orders[0]) - 1
+        for e in range(E):
+            ref = oracle.moments(w.problem, w.material, w.mat[e], w.nodes[e], *w.quad[e], K)
+            assert np.abs(m[e] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_inverted_element_status(env):
+    W = env["W"]
+    w = make_small(env, 0, 3, 3, (4, 4, 4), seed=3)
+    w["nodes"][1, 13] = (2.0, 2.0, 2.0)
+    out, off, st, _ = gpu_fill(env, w)
+    assert st[1] & 1 and st[0] == 0 and st[2] == 0
+
+
+def test_empty_batch(env):
+    torch, p2s = env["torch"], env["p2s"]
+    plan = env["ctx"].plan(0, 0, np.zeros(0, np.int32), np.zeros((0, 3), np.int32))
+    out, st = plan.execute(torch.zeros(1, dtype=torch.float64, device="cuda"),
+                           torch.zeros(1, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert out.numel() == 0 and st.numel() == 0
+
+
+def test_argument_errors(env):
+    p2s = env["p2s"]
+    ctx = env["ctx"]
+    with pytest.raises(p2s.P2SError, match="order"):
+        ctx.plan(0, 0, [9], [[4, 4, 4]])
+    with pytest.raises(p2s.P2SError, match="Gauss"):
+        ctx.plan(0, 0, [4], [[33, 4, 4]])
+    with pytest.raises(p2s.P2SError, match="isotropic"):
+        ctx.plan(0, 1, [4], [[4, 4, 4]])
+    with pytest.raises(p2s.P2SError, match="material"):
+        ctx.plan(0, 7, [4], [[4, 4, 4]])
+    with pytest.raises(p2s.P2SError, match="one order"):
+        ctx.plan(0, 3, [4, 5], [[4, 4, 4], [4, 4, 4]])
+
+
+def test_vector_n6_full_size_sampled(env):
+    """The full 4096-element vector workload in the benchmark's launch
+    configuration: sampled elements against the oracle, symmetry of every
+    element matrix, and bitwise repeatability."""
+    torch, W = env["torch"], env["W"]
+    w = W.make("vector_n6")
+    plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
+    nodes = torch.from_numpy(w.nodes).cuda()
+    mat = torch.from_numpy(w.mat).cuda()
+    out, st = plan.execute(nodes, mat)
+    out2, _ = plan.execute(nodes, mat)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    assert torch.equal(out, out2)
+    nd = 540
+    M = out.view(w.E, nd, nd)
+    asym = (M - M.transpose(1, 2)).abs().amax(dim=(1, 2)) / M.abs().amax(dim=(1, 2))
+    assert float(asym.max()) <= 1e-13
+    pick = [0, 1234, 4095]
+    sub = W.subset(w, pick)
+    ref, roff, _ = env["oracle"].fill(sub.problem, sub.material, sub.nodes, sub.mat, sub.orders, sub.quad)
+    for i, e in enumerate(pick):
+        x = M[e].cpu().numpy().reshape(-1)
+        y = ref[roff[i]:roff[i + 1]]
+        err = np.linalg.norm(x - y) / np.linalg.norm(y)
+        print("element", e, "rel err %.3e" % err, flush=True)
+        assert err <= TOL
