@@ -60,6 +60,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="vector_n6", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="before the fill, run a plain 1 GiB device copy three times (a known-size "
+                         "reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the fill is element-parallel and this build runs on a "
@@ -79,6 +82,13 @@ def main():
     out = torch.empty(int(plan.offsets[-1]), dtype=torch.float64, device=dev)
     status = torch.empty(w.E, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         plan.execute(nodes, mat, out, status)

@@ -23,7 +23,7 @@ using namespace p2s;
 struct p2s_ctx_s {
     int device = 0;
     double *d_tab = nullptr;
-    Term *d_terms = nullptr;  // [2 problems][9 blocks][MAX_TERMS]
+    BlockDesc *d_blocks = nullptr;  // [2 problems][9 blocks]
     std::string err;
 };
 
@@ -174,6 +174,29 @@ static void vector_terms(int i, int j, Term *t)
     t[n++] = m;
 }
 
+// Sort a block's terms by (tw, tv) and mark the groups (see BlockDesc).
+static BlockDesc make_block(const Term *t, int n)
+{
+    BlockDesc b{};
+    std::vector<Term> v(t, t + n);
+    std::stable_sort(v.begin(), v.end(), [](const Term &x, const Term &y) {
+        return x.tw != y.tw ? x.tw < y.tw : x.tv < y.tv;
+    });
+    b.nterm = (int8_t)n;
+    int g = 0;
+    for (int s = 0; s < n; ++s) {
+        b.t[s] = v[s];
+        if (s == 0 || v[s].tw != v[s - 1].tw || v[s].tv != v[s - 1].tv) b.gstart[g++] = (int8_t)s;
+    }
+    b.gstart[g] = (int8_t)n;
+    b.ngroup = (int8_t)g;
+    for (int k = 0; k < g; ++k) {
+        const bool last = k + 1 == g || v[b.gstart[k + 1]].tw != v[b.gstart[k]].tw;
+        b.cflag[k] = last ? 1 : 0;
+    }
+    return b;
+}
+
 // ---------------------------------------------------------------------------
 
 extern "C" {
@@ -236,17 +259,24 @@ int p2s_create(p2s_ctx *out, int device)
     }
     std::vector<double> tab(TAB_SIZE);
     build_tables(tab.data());
-    std::vector<Term> terms(2 * 9 * MAX_TERMS);
-    scalar_terms(terms.data());
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) vector_terms(i, j, terms.data() + (9 + i * 3 + j) * MAX_TERMS);
+    std::vector<BlockDesc> blocks(2 * 9);
+    {
+        Term t[MAX_TERMS];
+        scalar_terms(t);
+        blocks[0] = make_block(t, 10);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                vector_terms(i, j, t);
+                blocks[9 + i * 3 + j] = make_block(t, 5);
+            }
+    }
     if (hipMalloc(&ctx->d_tab, sizeof(double) * TAB_SIZE) != hipSuccess ||
-        hipMalloc(&ctx->d_terms, sizeof(Term) * terms.size()) != hipSuccess) {
+        hipMalloc(&ctx->d_blocks, sizeof(BlockDesc) * blocks.size()) != hipSuccess) {
         p2s_destroy(ctx);
         return fail(nullptr, P2S_ENOMEM, "p2s_create: table allocation failed");
     }
     if (hipMemcpy(ctx->d_tab, tab.data(), sizeof(double) * TAB_SIZE, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(ctx->d_terms, terms.data(), sizeof(Term) * terms.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->d_blocks, blocks.data(), sizeof(BlockDesc) * blocks.size(), hipMemcpyHostToDevice) != hipSuccess ||
         prepare_kernels() != 0) {
         p2s_destroy(ctx);
         return fail(nullptr, P2S_EHIP, "p2s_create: table upload failed");
@@ -260,7 +290,7 @@ void p2s_destroy(p2s_ctx ctx)
     if (!ctx) return;
     hipSetDevice(ctx->device);
     if (ctx->d_tab) hipFree(ctx->d_tab);
-    if (ctx->d_terms) hipFree(ctx->d_terms);
+    if (ctx->d_blocks) hipFree(ctx->d_blocks);
     delete ctx;
 }
 
@@ -442,7 +472,7 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     const int problem = plan->terms.problem;
     const int F = num_fields(problem);
-    const Term *terms = ctx->d_terms + (problem == 0 ? 0 : 9 * MAX_TERMS);
+    const BlockDesc *terms = ctx->d_blocks + (problem == 0 ? 0 : 9);
     for (const Chunk &c : plan->chunks) {
         prof_begin(plan, 0, st);
         launch_coupling(problem, plan->d_desc, c.e0, c.count, nodes, material, plan->terms.material,

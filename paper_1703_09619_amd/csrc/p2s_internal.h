@@ -31,13 +31,6 @@ constexpr int GX_SIZE = (MAXQ + 1) * MAXQ;
 constexpr int LEGW_STRIDE_Q = KPAD * MAXQ;
 constexpr int LEGW_SIZE = (MAXQ + 1) * LEGW_STRIDE_Q;
 
-// Offsets of the device table buffer (in doubles).
-constexpr int TAB_LIN = 0;
-constexpr int TAB_GX = TAB_LIN + LIN_SIZE;
-constexpr int TAB_GW = TAB_GX + GX_SIZE;
-constexpr int TAB_LEGW = TAB_GW + GX_SIZE;
-constexpr int TAB_SIZE = TAB_LEGW + LEGW_SIZE;
-
 P2S_HD constexpr int fam_dim(int fam, int N) { return fam == PSI ? N - 1 : N; }
 
 // Legendre degrees present in the expansion of family member m.
@@ -64,6 +57,49 @@ P2S_HD constexpr uint32_t prod_mask(int fx, int m1, int fy, int m2)
     return r;
 }
 
+P2S_HD constexpr int popcount32(uint32_t v)
+{
+    int c = 0;
+    for (; v; v &= v - 1u) ++c;
+    return c;
+}
+
+// Packed linearization tables: for order N and family pair (X,Y), the
+// structurally nonzero coefficients lin[X,Y][p1][p2][q] in the order
+// p1 < dim(X,N), p2 < dim(Y,N), q ascending -- the order in which the
+// unrolled last contraction stage consumes them.
+P2S_HD constexpr int packed_before(int X, int Y, int N, int P1, int P2)
+{
+    int c = 0;
+    for (int p1 = 0; p1 < fam_dim(X, N); ++p1)
+        for (int p2 = 0; p2 < fam_dim(Y, N); ++p2) {
+            if (p1 == P1 && p2 == P2) return c;
+            c += popcount32(prod_mask(X, p1, Y, p2));
+        }
+    return c;
+}
+P2S_HD constexpr int packed_count(int X, int Y, int N) { return packed_before(X, Y, N, -1, -1); }
+// offset of the (N, X, Y) table inside the packed region, N = 2..MAXN
+P2S_HD constexpr int packed_offset(int N, int X, int Y)
+{
+    int o = 0;
+    for (int n = 2; n <= MAXN; ++n)
+        for (int t = 0; t < NTYPE; ++t) {
+            if (n == N && t == 3 * X + Y) return o;
+            o += (packed_count(t / 3, t % 3, n) + 1) & ~1;  // keep 16-byte alignment
+        }
+    return o;
+}
+constexpr int PACKED_SIZE = packed_offset(MAXN + 1, 0, 0);
+
+// Offsets of the device table buffer (in doubles).
+constexpr int TAB_LIN = 0;
+constexpr int TAB_GX = TAB_LIN + LIN_SIZE;
+constexpr int TAB_GW = TAB_GX + GX_SIZE;
+constexpr int TAB_LEGW = TAB_GW + GX_SIZE;
+constexpr int TAB_PACK = TAB_LEGW + LEGW_SIZE;
+constexpr int TAB_SIZE = TAB_PACK + PACKED_SIZE;
+
 // One coupling term of a block (i,j): moment field, sign, and the family
 // pair (test, trial) on each axis.  Scale selects stiff_scale (0) or
 // mass_scale (1).
@@ -72,6 +108,17 @@ struct Term {
 };
 
 constexpr int MAX_TERMS = 10;  // scalar: 9 stiffness + 1 mass; vector: 5 per block
+
+// Terms of one block (i,j), sorted so that terms sharing the (v, w) family
+// pairs are adjacent.  A "group" is a run of terms with equal (tv, tw): their
+// first-stage results are summed before the second stage.  cflag[g] marks the
+// last group of a run with equal tw: the last stage runs once per such run.
+struct BlockDesc {
+    int8_t nterm, ngroup;
+    int8_t gstart[MAX_TERMS + 1];
+    int8_t cflag[MAX_TERMS];
+    Term t[MAX_TERMS];
+};
 
 // Mirrors of the public enums and status bits (include/p2s.h).
 enum MatKind : int { MAT_SINCOSEXP = 0, MAT_ROTDIAG = 1, MAT_PLANEWAVE = 2, ALPHA_SAMPLED = 3 };

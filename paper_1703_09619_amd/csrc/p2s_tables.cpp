@@ -120,6 +120,20 @@ void build_tables(double *tab)
                     linearization(xf, m1, yf, m2,
                                   tab + TAB_LIN + (3 * xf + yf) * LIN_STRIDE_T +
                                       m1 * LIN_STRIDE_M1 + m2 * KPAD);
+    // packed copies in consumption order of the last contraction stage
+    for (int N = 2; N <= MAXN; ++N)
+        for (int X = 0; X < NFAM; ++X)
+            for (int Y = 0; Y < NFAM; ++Y) {
+                double *dst = tab + TAB_PACK + packed_offset(N, X, Y);
+                const double *src = tab + TAB_LIN + (3 * X + Y) * LIN_STRIDE_T;
+                int n = 0;
+                for (int p1 = 0; p1 < fam_dim(X, N); ++p1)
+                    for (int p2 = 0; p2 < fam_dim(Y, N); ++p2) {
+                        const uint32_t m = prod_mask(X, p1, Y, p2);
+                        for (int q = 0; q < KPAD; ++q)
+                            if ((m >> q) & 1u) dst[n++] = src[p1 * LIN_STRIDE_M1 + p2 * KPAD + q];
+                    }
+            }
     double L[KPAD];
     for (int Q = 1; Q <= MAXQ; ++Q) {
         double *x = tab + TAB_GX + Q * MAXQ;
