@@ -23,7 +23,6 @@ using namespace p2s;
 struct p2s_ctx_s {
     int device = 0;
     double *d_tab = nullptr;
-    BlockDesc *d_blocks = nullptr;  // [2 problems][9 blocks]
     std::string err;
 };
 
@@ -100,104 +99,6 @@ static int fail(p2s_ctx ctx, int code, const char *fmt, ...)
     } while (0)
 
 // ---------------------------------------------------------------------------
-// Coupling terms of eq. (2) for each block (i,j).
-
-static int sym_index(int a, int b)
-{
-    if (a == b) return a;
-    const int lo = std::min(a, b), hi = std::max(a, b);
-    return lo == 0 ? (hi == 1 ? 3 : 4) : 5;
-}
-
-static int levi_civita(int a, int b, int c)
-{
-    if (a == b || b == c || a == c) return 0;
-    return ((a == 0 && b == 1) || (a == 1 && b == 2) || (a == 2 && b == 0)) ? 1 : -1;
-}
-
-// Scalar problem: one block, 9 stiffness terms (a,b) with coupling
-// eps detJ (J^-1 J^-T)_ab, derivative along axis a on the test side and b on
-// the trial side; one mass term eps detJ.
-static void scalar_terms(Term *t)
-{
-    int n = 0;
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-            Term x{};
-            x.field = (int8_t)sym_index(a, b);
-            x.sign = 1;
-            x.scale = 0;
-            int8_t *ty[3] = {&x.tu, &x.tv, &x.tw};
-            for (int ax = 0; ax < 3; ++ax)
-                *ty[ax] = (int8_t)(3 * (a == ax ? DPHI : PHI) + (b == ax ? DPHI : PHI));
-            t[n++] = x;
-        }
-    Term m{};
-    m.field = 6;
-    m.sign = 1;
-    m.scale = 1;
-    m.tu = m.tv = m.tw = 3 * PHI + PHI;
-    t[n++] = m;
-}
-
-// Vector problem, block (i,j): E_i = f e_i with f = psi along axis i and phi
-// elsewhere.  (curl f e_i)_c = eps_{c e i} d_e f, e = 3 - c - i, so each block
-// has 4 curl terms (c != i, d != j) with coupling (J^T J / detJ)_cd and sign
-// eps_{c e i} eps_{d f j}, plus one mass term (detJ J^-1 eps J^-T)_ij.
-static void vector_terms(int i, int j, Term *t)
-{
-    int n = 0;
-    for (int c = 0; c < 3; ++c) {
-        if (c == i) continue;
-        for (int d = 0; d < 3; ++d) {
-            if (d == j) continue;
-            const int e = 3 - c - i, f = 3 - d - j;
-            Term x{};
-            x.field = (int8_t)sym_index(c, d);
-            x.sign = (int8_t)(levi_civita(c, e, i) * levi_civita(d, f, j));
-            x.scale = 0;
-            int8_t *ty[3] = {&x.tu, &x.tv, &x.tw};
-            for (int ax = 0; ax < 3; ++ax) {
-                const int X = ax == i ? PSI : (ax == e ? DPHI : PHI);
-                const int Y = ax == j ? PSI : (ax == f ? DPHI : PHI);
-                *ty[ax] = (int8_t)(3 * X + Y);
-            }
-            t[n++] = x;
-        }
-    }
-    Term m{};
-    m.field = (int8_t)(6 + sym_index(i, j));
-    m.sign = 1;
-    m.scale = 1;
-    int8_t *ty[3] = {&m.tu, &m.tv, &m.tw};
-    for (int ax = 0; ax < 3; ++ax) *ty[ax] = (int8_t)(3 * (ax == i ? PSI : PHI) + (ax == j ? PSI : PHI));
-    t[n++] = m;
-}
-
-// Sort a block's terms by (tw, tv) and mark the groups (see BlockDesc).
-static BlockDesc make_block(const Term *t, int n)
-{
-    BlockDesc b{};
-    std::vector<Term> v(t, t + n);
-    std::stable_sort(v.begin(), v.end(), [](const Term &x, const Term &y) {
-        return x.tw != y.tw ? x.tw < y.tw : x.tv < y.tv;
-    });
-    b.nterm = (int8_t)n;
-    int g = 0;
-    for (int s = 0; s < n; ++s) {
-        b.t[s] = v[s];
-        if (s == 0 || v[s].tw != v[s - 1].tw || v[s].tv != v[s - 1].tv) b.gstart[g++] = (int8_t)s;
-    }
-    b.gstart[g] = (int8_t)n;
-    b.ngroup = (int8_t)g;
-    for (int k = 0; k < g; ++k) {
-        const bool last = k + 1 == g || v[b.gstart[k + 1]].tw != v[b.gstart[k]].tw;
-        b.cflag[k] = last ? 1 : 0;
-    }
-    return b;
-}
-
-// ---------------------------------------------------------------------------
 
 extern "C" {
 
@@ -259,24 +160,11 @@ int p2s_create(p2s_ctx *out, int device)
     }
     std::vector<double> tab(TAB_SIZE);
     build_tables(tab.data());
-    std::vector<BlockDesc> blocks(2 * 9);
-    {
-        Term t[MAX_TERMS];
-        scalar_terms(t);
-        blocks[0] = make_block(t, 10);
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                vector_terms(i, j, t);
-                blocks[9 + i * 3 + j] = make_block(t, 5);
-            }
-    }
-    if (hipMalloc(&ctx->d_tab, sizeof(double) * TAB_SIZE) != hipSuccess ||
-        hipMalloc(&ctx->d_blocks, sizeof(BlockDesc) * blocks.size()) != hipSuccess) {
+    if (hipMalloc(&ctx->d_tab, sizeof(double) * TAB_SIZE) != hipSuccess) {
         p2s_destroy(ctx);
         return fail(nullptr, P2S_ENOMEM, "p2s_create: table allocation failed");
     }
     if (hipMemcpy(ctx->d_tab, tab.data(), sizeof(double) * TAB_SIZE, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(ctx->d_blocks, blocks.data(), sizeof(BlockDesc) * blocks.size(), hipMemcpyHostToDevice) != hipSuccess ||
         prepare_kernels() != 0) {
         p2s_destroy(ctx);
         return fail(nullptr, P2S_EHIP, "p2s_create: table upload failed");
@@ -290,7 +178,6 @@ void p2s_destroy(p2s_ctx ctx)
     if (!ctx) return;
     hipSetDevice(ctx->device);
     if (ctx->d_tab) hipFree(ctx->d_tab);
-    if (ctx->d_blocks) hipFree(ctx->d_blocks);
     delete ctx;
 }
 
@@ -472,7 +359,6 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     const int problem = plan->terms.problem;
     const int F = num_fields(problem);
-    const BlockDesc *terms = ctx->d_blocks + (problem == 0 ? 0 : 9);
     for (const Chunk &c : plan->chunks) {
         prof_begin(plan, 0, st);
         launch_coupling(problem, plan->d_desc, c.e0, c.count, nodes, material, plan->terms.material,
@@ -497,12 +383,12 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         }
         prof_begin(plan, 2, st);
         if (plan->uniform) {
-            launch_contract(problem, plan->N, plan->d_desc, nullptr, c.e0, c.count, ctx->d_tab, terms,
+            launch_contract(problem, plan->N, plan->d_desc, nullptr, c.e0, c.count, ctx->d_tab,
                             plan->d_mom, out, status, plan->terms.stiff_scale, plan->terms.mass_scale, st);
         } else {
             for (const auto &cl : c.classes)
                 launch_contract(problem, (int)cl[0], plan->d_desc, plan->d_elist, cl[1], cl[2], ctx->d_tab,
-                                terms, plan->d_mom, out, status, plan->terms.stiff_scale,
+                                plan->d_mom, out, status, plan->terms.stiff_scale,
                                 plan->terms.mass_scale, st);
         }
         prof_end(plan, 2, st);

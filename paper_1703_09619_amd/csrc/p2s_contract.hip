@@ -1,0 +1,527 @@
+// p2s_contract.hip -- the contraction stage of the product-to-sum fill,
+// eq. (4) of the paper: M = sum_s sum_{k,l,q} Cu Cv Cw I_s, applied mode by
+// mode, for gfx950 (wave64).
+//
+// One workgroup per (element, row component I, first-axis test index m1):
+// it produces rows (m1, n1, p1) of component I against column components
+// J >= I (the element matrix is symmetric; the part below the diagonal is
+// stored as the mirror image).  For a block (I,J) the coupling terms are
+// grouped: a group shares the (v, w) family pairs, a run shares the w pair.
+//   stage A  A_g[m2][l][q] = sum_{s in g} sign_s sum_k Cu_s[m1][m2][k] I_s[k][l][q]
+//            one thread per (group, l, q); each moment is loaded once and
+//            reused for every m2                                     (LDS)
+//   stage B  B[q] += sum_l Cv_g[n1][n2][l] A_g[m2][l][q]  over the groups
+//            of a run; one lane per (m2, n1, n2)                   (registers)
+//   stage C  acc[p1][p2] += sum_q Cw_run[p1][p2][q] B[q]           (registers)
+// The term structure of every block is computed at compile time, so the
+// family pairs, fields and signs are constants; stage C's sparsity is
+// unrolled and its coefficients are scalar loads from a packed table.
+// The finished tile goes through LDS so that every store instruction writes
+// whole rows (1 KiB per wave instruction).
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "p2s_internal.h"
+#include "p2s_kernels.h"
+
+namespace p2s {
+
+// ---------------------------------------------------------------------------
+// Compile-time structure
+
+struct MaskTableC {
+    uint32_t m[NTYPE][MAXN][MAXN];
+    constexpr MaskTableC() : m()
+    {
+        for (int t = 0; t < NTYPE; ++t)
+            for (int a = 0; a < MAXN; ++a)
+                for (int b = 0; b < MAXN; ++b) m[t][a][b] = prod_mask(t / 3, a, t % 3, b);
+    }
+};
+__constant__ MaskTableC c_cmasks = MaskTableC();
+
+struct PackIndex {
+    int16_t before[MAXN + 1][NTYPE][MAXN][MAXN];
+    constexpr PackIndex() : before()
+    {
+        for (int n = 2; n <= MAXN; ++n)
+            for (int t = 0; t < NTYPE; ++t) {
+                int c = 0;
+                for (int p1 = 0; p1 < fam_dim(t / 3, n); ++p1)
+                    for (int p2 = 0; p2 < fam_dim(t % 3, n); ++p2) {
+                        before[n][t][p1][p2] = (int16_t)c;
+                        c += popcount32(prod_mask(t / 3, p1, t % 3, p2));
+                    }
+            }
+    }
+};
+constexpr PackIndex kPackIndex = PackIndex();
+
+struct PackOffsets {
+    int off[MAXN + 1][NTYPE];
+    constexpr PackOffsets() : off()
+    {
+        int o = 0;  // same running layout as packed_offset()
+        for (int n = 2; n <= MAXN; ++n)
+            for (int t = 0; t < NTYPE; ++t) {
+                off[n][t] = o;
+                o += (packed_count(t / 3, t % 3, n) + 1) & ~1;
+            }
+    }
+};
+constexpr PackOffsets kPackOffsets = PackOffsets();
+
+constexpr int MAX_TERMS = 10;  // scalar: 9 stiffness + 1 mass; vector: 5 per block
+
+struct TermC {
+    int field, sign, scale, tu, tv, tw;
+};
+
+struct BlockC {
+    int nterm = 0, ngroup = 0;
+    int gstart[MAX_TERMS + 1] = {};
+    int cflag[MAX_TERMS] = {};
+    TermC t[MAX_TERMS] = {};
+};
+
+constexpr int sym_c(int a, int b)
+{
+    return a == b ? a : ((a < b ? a : b) == 0 ? ((a > b ? a : b) == 1 ? 3 : 4) : 5);
+}
+
+constexpr int levi_c(int a, int b, int c)
+{
+    return (a == b || b == c || a == c) ? 0
+         : (((a == 0 && b == 1) || (a == 1 && b == 2) || (a == 2 && b == 0)) ? 1 : -1);
+}
+
+// Coupling terms of block (i,j) of eq. (2), sorted by (tw, tv) and grouped.
+// Scalar: 9 stiffness terms (a,b) with field eps detJ (J^-1 J^-T)_ab,
+//   derivative on axis a (test) and b (trial), plus the mass term.
+// Vector: E_i = f e_i, f = psi along axis i, phi elsewhere; the reference
+//   curl (curl f e_i)_c = eps_{c e i} d_e f (e = 3-c-i) gives 4 curl terms
+//   (c != i, d != j) with field (J^T J/detJ)_cd and sign eps_{cei} eps_{dfj},
+//   plus the mass term with field (detJ J^-1 eps J^-T)_ij.
+constexpr BlockC make_block_c(int prob, int i, int j)
+{
+    BlockC b{};
+    TermC t[MAX_TERMS] = {};
+    int n = 0;
+    if (prob == 0) {
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) {
+                t[n].field = sym_c(a, c);
+                t[n].sign = 1;
+                t[n].scale = 0;
+                t[n].tu = 3 * (a == 0 ? DPHI : PHI) + (c == 0 ? DPHI : PHI);
+                t[n].tv = 3 * (a == 1 ? DPHI : PHI) + (c == 1 ? DPHI : PHI);
+                t[n].tw = 3 * (a == 2 ? DPHI : PHI) + (c == 2 ? DPHI : PHI);
+                ++n;
+            }
+        t[n].field = 6;
+        t[n].sign = 1;
+        t[n].scale = 1;
+        t[n].tu = t[n].tv = t[n].tw = 3 * PHI + PHI;
+        ++n;
+    } else {
+        for (int c = 0; c < 3; ++c) {
+            if (c == i) continue;
+            for (int d = 0; d < 3; ++d) {
+                if (d == j) continue;
+                const int e = 3 - c - i, f = 3 - d - j;
+                int ty[3] = {0, 0, 0};
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int X = ax == i ? PSI : (ax == e ? DPHI : PHI);
+                    const int Y = ax == j ? PSI : (ax == f ? DPHI : PHI);
+                    ty[ax] = 3 * X + Y;
+                }
+                t[n].field = sym_c(c, d);
+                t[n].sign = levi_c(c, e, i) * levi_c(d, f, j);
+                t[n].scale = 0;
+                t[n].tu = ty[0];
+                t[n].tv = ty[1];
+                t[n].tw = ty[2];
+                ++n;
+            }
+        }
+        int ty[3] = {0, 0, 0};
+        for (int ax = 0; ax < 3; ++ax) ty[ax] = 3 * (ax == i ? PSI : PHI) + (ax == j ? PSI : PHI);
+        t[n].field = 6 + sym_c(i, j);
+        t[n].sign = 1;
+        t[n].scale = 1;
+        t[n].tu = ty[0];
+        t[n].tv = ty[1];
+        t[n].tw = ty[2];
+        ++n;
+    }
+    // stable insertion sort by (tw, tv)
+    for (int a = 1; a < n; ++a) {
+        TermC x = t[a];
+        int p = a - 1;
+        while (p >= 0 && (t[p].tw > x.tw || (t[p].tw == x.tw && t[p].tv > x.tv))) {
+            t[p + 1] = t[p];
+            --p;
+        }
+        t[p + 1] = x;
+    }
+    b.nterm = n;
+    int g = 0;
+    for (int s = 0; s < n; ++s) {
+        b.t[s] = t[s];
+        if (s == 0 || t[s].tw != t[s - 1].tw || t[s].tv != t[s - 1].tv) b.gstart[g++] = s;
+    }
+    b.gstart[g] = n;
+    b.ngroup = g;
+    for (int k = 0; k < g; ++k)
+        b.cflag[k] = (k + 1 == g || t[b.gstart[k + 1]].tw != t[b.gstart[k]].tw) ? 1 : 0;
+    return b;
+}
+
+template <int PROB, int I, int J>
+struct BlockOf {
+    static constexpr BlockC B = make_block_c(PROB, I, J);
+};
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+template <int PROB, int N, int I>
+struct CS {
+    static constexpr int K = 2 * N - 1;
+    static constexpr int KS = K + 1;  // LDS row stride (16-byte aligned rows)
+    static constexpr int NC = num_comp(PROB);
+    static constexpr int NDOF = num_dofs(PROB, N);
+    static constexpr int NM_I = comp_dim(PROB, N, I, 0);
+    static constexpr int NN_I = comp_dim(PROB, N, I, 1);
+    static constexpr int NP_I = comp_dim(PROB, N, I, 2);
+    static constexpr int max_over_j(int what)
+    {
+        int m = 0;
+        for (int j = I; j < NC; ++j) {
+            int v = 0;
+            if (what == 0) v = comp_dim(PROB, N, j, 0) * NN_I * comp_dim(PROB, N, j, 1);  // lane tasks
+            if (what == 1) v = make_block_c(PROB, I, j).ngroup;
+            if (what == 2) v = comp_dim(PROB, N, j, 1);
+            if (what == 3) v = comp_dim(PROB, N, j, 0) * comp_dim(PROB, N, j, 1) * comp_dim(PROB, N, j, 2);
+            m = cmax(m, v);
+        }
+        return m;
+    }
+    static constexpr int THREADS = ((max_over_j(0) + 63) / 64) * 64;
+    static constexpr int MAXG = max_over_j(1);
+    static constexpr int A_DOUBLES = N * K * KS;                    // stage-A result per group
+    static constexpr int C_DOUBLES = NN_I * max_over_j(2) * KS;      // stage-B coefficients per group
+    static constexpr int GROUP_DOUBLES = A_DOUBLES + C_DOUBLES;
+    static constexpr int G = cmax(1, cmin(MAXG, 7936 / GROUP_DOUBLES));  // groups per LDS batch (~62 KiB)
+    static constexpr int TILE_MIN = (max_over_j(3) + 2) * NP_I;     // one n1 of the store tile
+    static constexpr int BUF = cmax(G * GROUP_DOUBLES, TILE_MIN);
+    static constexpr int SA = ((K * K + 63) / 64) * 64;              // stage-A workers per group
+};
+
+// constant address space: loads through it become scalar (SMEM) loads
+typedef __attribute__((address_space(4))) const double cdouble;
+
+template <int N, int X, int Y, int P1, int P2>
+__device__ __forceinline__ void stage_c_one(double (&acc)[N][N], const double (&bv)[2 * N - 1],
+                                            cdouble *__restrict__ tb)
+{
+    if constexpr (P1 < fam_dim(X, N) && P2 < fam_dim(Y, N)) {
+        constexpr uint32_t msk = prod_mask(X, P1, Y, P2);
+        constexpr int base = kPackIndex.before[N][3 * X + Y][P1][P2];
+#pragma unroll
+        for (int q = 0; q < 2 * N - 1; ++q)
+            if ((msk >> q) & 1u)
+                acc[P1][P2] = fma(tb[base + popcount32(msk & ((1u << q) - 1u))], bv[q], acc[P1][P2]);
+    }
+}
+
+template <int N, int X, int Y, int... Is>
+__device__ __forceinline__ void stage_c_all(double (&acc)[N][N], const double (&bv)[2 * N - 1],
+                                            cdouble *__restrict__ tb, std::integer_sequence<int, Is...>)
+{
+    (stage_c_one<N, X, Y, Is / N, Is % N>(acc, bv, tb), ...);
+}
+
+template <int N, int T>
+__device__ __forceinline__ void stage_c(double (&acc)[N][N], const double (&bv)[2 * N - 1],
+                                        const double *__restrict__ pack)
+{
+    constexpr int X = T / 3, Y = T % 3;
+    constexpr int off = kPackOffsets.off[N][T];
+    static_assert(off == packed_offset(N, X, Y), "packed table layout");
+    cdouble *tb = (cdouble *)(pack + off);
+    // keep the table base opaque to loop-invariant motion so that every
+    // coefficient is a scalar load at an immediate offset
+    asm volatile("" : "+s"(tb));
+    stage_c_all<N, X, Y>(acc, bv, tb, std::make_integer_sequence<int, N * N>{});
+}
+
+// Work-group id -> logical work item, so that consecutive items (the row
+// tiles of one element, which share its moment tensors) run on the same XCD:
+// the hardware deals work-group ids round-robin over the 8 XCDs.
+__device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t total_padded)
+{
+    const int64_t per = total_padded >> 3;
+    return (w & 7) * per + (w >> 3);
+}
+
+template <int PROB, int N, int I>
+__global__ __launch_bounds__((CS<PROB, N, I>::THREADS)) void k_contract(
+    const ElemDesc *__restrict__ desc, const int32_t *__restrict__ elist, int64_t e0, int64_t nitems,
+    int64_t padded, const double *__restrict__ tab, const double *__restrict__ mom,
+    double *__restrict__ out, uint32_t *__restrict__ status, double sK, double sM)
+{
+    using S = CS<PROB, N, I>;
+    constexpr int K = S::K, KS = S::KS, NC = S::NC, NDOF = S::NDOF, G = S::G;
+    constexpr int NN_I = S::NN_I, NP_I = S::NP_I;
+    const int64_t item = xcd_remap(blockIdx.x, padded);
+    if (item >= nitems) return;
+    const int64_t eidx = e0 + item / S::NM_I;
+    const int64_t e = elist ? (int64_t)elist[eidx] : eidx;
+    const int m1 = (int)(item % S::NM_I);
+    const ElemDesc d = desc[e];
+    const double *lin = tab + TAB_LIN;
+    const double *pack = tab + TAB_PACK;
+    const double *I0 = mom + d.mom_off;
+    double *obase = out + d.out_off;
+    __shared__ __attribute__((aligned(16))) double smem[S::BUF];
+    const int tid = threadIdx.x;
+    const int rowbase = comp_offset(PROB, N, I) + m1 * NN_I * NP_I;
+    bool bad = false;
+
+    static_for<I, NC>([&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        constexpr BlockC BK = BlockOf<PROB, I, J>::B;
+        constexpr int NM_J = comp_dim(PROB, N, J, 0), NN_J = comp_dim(PROB, N, J, 1),
+                      NP_J = comp_dim(PROB, N, J, 2);
+        constexpr int NBATCH = (BK.ngroup + G - 1) / G;
+        // symmetric: inside the diagonal block only m2 >= m1
+        const int m2lo = (J == I) ? m1 : 0;
+        const int nm = NM_J - m2lo;
+        const int T = nm * NN_I * NN_J;
+        const bool active = tid < T;
+        const int n2 = tid % NN_J;
+        const int m2 = m2lo + (tid / NN_J) % nm;
+        const int n1 = tid / (NN_J * nm);
+        double acc[N][N];
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) acc[a][b] = 0.0;
+        double bsum[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) bsum[q] = 0.0;
+
+        static_for<0, NBATCH>([&](auto Bc) {
+            constexpr int g0 = decltype(Bc)::value * G;
+            constexpr int ng = cmin(G, BK.ngroup - g0);
+            double *Abuf = smem;                    // [ng][N][K][KS]
+            double *Cbuf = smem + ng * S::A_DOUBLES;  // [ng][NN_I*NN_J][KS]
+            // stage-B coefficient rows of this batch into LDS
+            for (int x = tid; x < ng * NN_I * NN_J * K; x += S::THREADS) {
+                const int gl = x / (NN_I * NN_J * K);
+                const int r = x - gl * (NN_I * NN_J * K);
+                const int nn = r / K, l = r - (r / K) * K;
+                const int a1 = nn / NN_J, a2 = nn - (nn / NN_J) * NN_J;
+                int tv = 0;
+                static_for<0, ng>([&](auto gc) {
+                    constexpr int g = decltype(gc)::value;
+                    if (gl == g) tv = BK.t[BK.gstart[g0 + g]].tv;
+                });
+                Cbuf[gl * (NN_I * NN_J * KS) + nn * KS + l] =
+                    lin[tv * LIN_STRIDE_T + a1 * LIN_STRIDE_M1 + a2 * KPAD + l];
+            }
+            // stage A: worker w -> (group gl, entry lq); gl is wave-uniform
+            for (int w = tid; w < ng * S::SA; w += S::THREADS) {
+                const int gl = w / S::SA;
+                const int lq = w - gl * S::SA;
+                if (lq < K * K) {
+                    double a[N];
+#pragma unroll
+                    for (int mm = 0; mm < N; ++mm) a[mm] = 0.0;
+                    static_for<0, ng>([&](auto gc) {
+                        constexpr int g = decltype(gc)::value;
+                        if (gl != g) return;
+                        static_for<BK.gstart[g0 + g], BK.gstart[g0 + g + 1]>([&](auto sc_) {
+                            constexpr TermC t = BK.t[decltype(sc_)::value];
+                            const double sc = (t.scale ? sM : sK) * (double)t.sign;
+                            const double *Ip = I0 + (int64_t)t.field * K * K * K + lq;
+                            double v[K];
+#pragma unroll
+                            for (int k = 0; k < K; ++k) v[k] = Ip[k * K * K];
+                            const double *Cu = lin + t.tu * LIN_STRIDE_T + m1 * LIN_STRIDE_M1;
+#pragma unroll
+                            for (int mm = 0; mm < NM_J; ++mm) {
+                                if (mm >= m2lo) {
+                                    const uint32_t mk = c_cmasks.m[t.tu][m1][mm];
+                                    double xs = 0.0;
+#pragma unroll
+                                    for (int k = 0; k < K; ++k)
+                                        if ((mk >> k) & 1u) xs = fma(Cu[mm * KPAD + k], v[k], xs);
+                                    a[mm] = fma(sc, xs, a[mm]);
+                                }
+                            }
+                        });
+                    });
+                    const int l = lq / K, q = lq - (lq / K) * K;
+                    double *Ab = Abuf + gl * S::A_DOUBLES + l * KS + q;
+#pragma unroll
+                    for (int mm = 0; mm < NM_J; ++mm)
+                        if (mm >= m2lo) Ab[mm * K * KS] = a[mm];
+                }
+            }
+            __syncthreads();
+            if (active) {
+                static_for<0, ng>([&](auto gc) {
+                    constexpr int g = decltype(gc)::value;
+                    constexpr int tv = BK.t[BK.gstart[g0 + g]].tv;
+                    constexpr int tw = BK.t[BK.gstart[g0 + g]].tw;
+                    // stage B: two set bits of the degree mask per step
+                    uint32_t ml = c_cmasks.m[tv][n1][n2];
+                    const double *crow = Cbuf + g * (NN_I * NN_J * KS) + (n1 * NN_J + n2) * KS;
+                    const double *arow = Abuf + g * S::A_DOUBLES + m2 * K * KS;
+                    while (ml) {
+                        const int l0 = __ffs(ml) - 1;
+                        ml &= ml - 1u;
+                        const bool two = ml != 0u;
+                        const int l1 = two ? __ffs(ml) - 1 : l0;
+                        ml &= two ? ml - 1u : ml;
+                        const double c0 = crow[l0];
+                        const double c1 = two ? crow[l1] : 0.0;
+                        const double2 *r0 = reinterpret_cast<const double2 *>(arow + l0 * KS);
+                        const double2 *r1 = reinterpret_cast<const double2 *>(arow + l1 * KS);
+#pragma unroll
+                        for (int h = 0; h < KS / 2; ++h) {
+                            const double2 x0 = r0[h], x1 = r1[h];
+                            bsum[2 * h] = fma(c1, x1.x, fma(c0, x0.x, bsum[2 * h]));
+                            if (2 * h + 1 < K) bsum[2 * h + 1] = fma(c1, x1.y, fma(c0, x0.y, bsum[2 * h + 1]));
+                        }
+                    }
+                    if constexpr (BK.cflag[g0 + g] != 0) {
+                        stage_c<N, tw>(acc, bsum, pack);
+#pragma unroll
+                        for (int q = 0; q < K; ++q) bsum[q] = 0.0;
+                    }
+                });
+            }
+            __syncthreads();
+        });
+
+        // coalesced stores through LDS: the tile holds rows (n1, p1) and
+        // columns (m2, n2, p2), m2 >= m2lo; n1 goes in chunks that fit
+        {
+            const int W = nm * NN_J * NP_J;     // tile width
+            const int WS = W + 2 - (W & 1);     // padded row stride (even)
+            int cn = S::BUF / (WS * NP_I);
+            cn = cn < 1 ? 1 : cn;
+            const int colj = comp_offset(PROB, N, J) + m2lo * NN_J * NP_J;
+            // mirrored rows start after the diagonal slab m2 == m1 of block (I,I)
+            const int cmir = (J == I) ? NN_J * NP_J : 0;
+            for (int n1a = 0; n1a < NN_I; n1a += cn) {
+                const int n1b = n1a + cn < NN_I ? n1a + cn : NN_I;
+                const int nr = (n1b - n1a) * NP_I;
+                if (active && n1 >= n1a && n1 < n1b) {
+                    double *tl = smem + (n1 - n1a) * NP_I * WS + ((m2 - m2lo) * NN_J + n2) * NP_J;
+#pragma unroll
+                    for (int p1 = 0; p1 < NP_I; ++p1)
+#pragma unroll
+                        for (int p2 = 0; p2 < NP_J; ++p2) {
+                            bad |= !isfinite(acc[p1][p2]);
+                            tl[p1 * WS + p2] = acc[p1][p2];
+                        }
+                }
+                __syncthreads();
+                double *drow = obase + (int64_t)(rowbase + n1a * NP_I) * NDOF + colj;
+                const bool d16 = (NDOF % 2 == 0) && (W % 2 == 0) &&
+                                 ((reinterpret_cast<uintptr_t>(drow) & 15u) == 0);
+                if (d16) {
+                    const int hw = W / 2;
+                    for (int x = tid; x < nr * hw; x += S::THREADS) {
+                        const int r = x / hw, c = 2 * (x - r * hw);
+                        *reinterpret_cast<double2 *>(drow + (int64_t)r * NDOF + c) =
+                            *reinterpret_cast<const double2 *>(smem + r * WS + c);
+                    }
+                } else {
+                    for (int x = tid; x < nr * W; x += S::THREADS) {
+                        const int r = x / W, c = x - r * W;
+                        drow[(int64_t)r * NDOF + c] = smem[r * WS + c];
+                    }
+                }
+                // mirror: tile column c is output row colj + c, holding the nr
+                // contiguous values of columns rowbase + n1a*NP_I + r
+                double *mrow = obase + (int64_t)colj * NDOF + rowbase + n1a * NP_I;
+                const int nc = W - cmir;
+                const bool m16 = (NDOF % 2 == 0) && (nr % 2 == 0) &&
+                                 ((reinterpret_cast<uintptr_t>(mrow) & 15u) == 0);
+                if (m16) {
+                    const int hr = nr / 2;
+                    for (int x = tid; x < nc * hr; x += S::THREADS) {
+                        const int c = cmir + x / hr, r = 2 * (x - (x / hr) * hr);
+                        *reinterpret_cast<double2 *>(mrow + (int64_t)c * NDOF + r) =
+                            make_double2(smem[r * WS + c], smem[(r + 1) * WS + c]);
+                    }
+                } else {
+                    for (int x = tid; x < nc * nr; x += S::THREADS) {
+                        const int c = cmir + x / nr, r = x - (x / nr) * nr;
+                        mrow[(int64_t)c * NDOF + r] = smem[r * WS + c];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    });
+    if (__syncthreads_or(bad) && tid == 0) atomicOr(status + e, P2S_STATUS_NONFINITE_BIT);
+}
+
+template <int PROB, int N, int I>
+static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,
+                              const double *tab, const double *mom, double *out, uint32_t *status,
+                              double sK, double sM, hipStream_t st)
+{
+    using S = CS<PROB, N, I>;
+    const int64_t nitems = count * S::NM_I;
+    const int64_t padded = (nitems + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_contract<PROB, N, I>), dim3((unsigned)padded), dim3(S::THREADS), 0, st, desc,
+                       elist, e0, nitems, padded, tab, mom, out, status, sK, sM);
+}
+
+template <int PROB, int N>
+static void launch_contract_t(const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,
+                              const double *tab, const double *mom, double *out, uint32_t *status,
+                              double sK, double sM, hipStream_t st)
+{
+    launch_contract_i<PROB, N, 0>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+    if constexpr (PROB == 1) {
+        launch_contract_i<PROB, N, 1>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+        launch_contract_i<PROB, N, 2>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+    }
+}
+
+int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0,
+                    int64_t count, const double *tab, const double *mom, double *out, uint32_t *status,
+                    double sK, double sM, hipStream_t st)
+{
+    if (count <= 0) return 0;
+#define P2S_CASE(P, n)                                                                             \
+    if (problem == P && N == n) {                                                                  \
+        launch_contract_t<P, n>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);        \
+        return 0;                                                                                  \
+    }
+    P2S_CASE(0, 2) P2S_CASE(0, 3) P2S_CASE(0, 4) P2S_CASE(0, 5) P2S_CASE(0, 6) P2S_CASE(0, 7) P2S_CASE(0, 8)
+    P2S_CASE(1, 2) P2S_CASE(1, 3) P2S_CASE(1, 4) P2S_CASE(1, 5) P2S_CASE(1, 6) P2S_CASE(1, 7) P2S_CASE(1, 8)
+#undef P2S_CASE
+    return -1;
+}
+
+}  // namespace p2s

@@ -100,26 +100,6 @@ constexpr int TAB_LEGW = TAB_GW + GX_SIZE;
 constexpr int TAB_PACK = TAB_LEGW + LEGW_SIZE;
 constexpr int TAB_SIZE = TAB_PACK + PACKED_SIZE;
 
-// One coupling term of a block (i,j): moment field, sign, and the family
-// pair (test, trial) on each axis.  Scale selects stiff_scale (0) or
-// mass_scale (1).
-struct Term {
-    int8_t field, sign, tu, tv, tw, scale;
-};
-
-constexpr int MAX_TERMS = 10;  // scalar: 9 stiffness + 1 mass; vector: 5 per block
-
-// Terms of one block (i,j), sorted so that terms sharing the (v, w) family
-// pairs are adjacent.  A "group" is a run of terms with equal (tv, tw): their
-// first-stage results are summed before the second stage.  cflag[g] marks the
-// last group of a run with equal tw: the last stage runs once per such run.
-struct BlockDesc {
-    int8_t nterm, ngroup;
-    int8_t gstart[MAX_TERMS + 1];
-    int8_t cflag[MAX_TERMS];
-    Term t[MAX_TERMS];
-};
-
 // Mirrors of the public enums and status bits (include/p2s.h).
 enum MatKind : int { MAT_SINCOSEXP = 0, MAT_ROTDIAG = 1, MAT_PLANEWAVE = 2, ALPHA_SAMPLED = 3 };
 constexpr uint32_t P2S_STATUS_DETJ_BIT = 1u;

@@ -19,7 +19,7 @@ void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t coun
 void launch_moments(int problem, int maxN, int maxQu, int maxQuv, const ElemDesc *desc, int64_t e0,
                     int64_t count, const double *alpha, const double *tab, double *mom, hipStream_t st);
 int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0,
-                    int64_t count, const double *tab, const BlockDesc *terms, const double *mom, double *out,
-                    uint32_t *status, double sK, double sM, hipStream_t st);
+                    int64_t count, const double *tab, const double *mom, double *out, uint32_t *status,
+                    double sK, double sM, hipStream_t st);
 
 }  // namespace p2s
