@@ -155,6 +155,33 @@ void p2s_plan_destroy(p2s_plan plan);
 int p2s_plan_profile(p2s_plan plan, int enable);
 int p2s_plan_profile_read(p2s_plan plan, double *ms, int64_t *launches);
 
+/* Schedule of the contraction stage.  mode 0: one launch per order class
+ * (per row component for the vector problem), one workgroup per row tile;
+ * mode 1 (scalar problem): one persistent launch of wgs_per_cu workgroups
+ * per compute unit that take row tiles from a list sorted by decreasing
+ * cost (longest first) through an atomic counter.  Plans of mixed orders of
+ * the scalar problem start in mode 1, others in mode 0. */
+int p2s_plan_set_schedule(p2s_plan plan, int mode, int wgs_per_cu);
+int p2s_plan_get_schedule(p2s_plan plan, int *mode, int *wgs_per_cu);
+
+/* Autotuner: times every candidate schedule on these buffers (one warm-up
+ * and three timed executions each, HIP events on `stream`), keeps the
+ * fastest, and records it in the JSON file cache_path [host] (keyed by
+ * device, problem, order and rule histograms, E); a later call with the
+ * same key reads the choice instead of timing.  cache_path may be NULL.
+ * best_ms [host], may be NULL, receives the chosen schedule's time.
+ * Synchronizes the stream. */
+int p2s_plan_autotune(p2s_plan plan, const double *nodes, const double *material, double *out,
+                      uint32_t *status, void *stream, const char *cache_path, double *best_ms);
+
+/* Graph capture: records one execution with these buffers into a HIP
+ * graph held by the plan (stream must not be the NULL stream);
+ * p2s_plan_replay launches it on `stream`.  The graph keeps the buffer
+ * addresses given at capture. */
+int p2s_plan_capture(p2s_plan plan, const double *nodes, const double *material, double *out,
+                     uint32_t *status, void *stream);
+int p2s_plan_replay(p2s_plan plan, void *stream);
+
 /* One-shot fill: plan create + execute + destroy (the plan is destroyed
  * after the stream has finished the work, so this call synchronizes the
  * stream).  Arguments as above. */

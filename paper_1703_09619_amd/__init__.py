@@ -33,6 +33,8 @@ EXPORTS = (
     "p2s_plan_create", "p2s_plan_execute", "p2s_plan_workspace_bytes", "p2s_plan_destroy",
     "p2s_fill_element_matrices", "p2s_plan_coupling", "p2s_plan_moments",
     "p2s_gauss_rule", "p2s_linearization", "p2s_plan_profile", "p2s_plan_profile_read",
+    "p2s_plan_set_schedule", "p2s_plan_get_schedule", "p2s_plan_autotune", "p2s_plan_capture",
+    "p2s_plan_replay",
 )
 
 
@@ -76,11 +78,18 @@ def load():
         lib.p2s_plan_moments.argtypes = [vp, vp, vp, vp, vp]
         lib.p2s_plan_profile.argtypes = [vp, i32]
         lib.p2s_plan_profile_read.argtypes = [vp, vp, vp]
+        lib.p2s_plan_set_schedule.argtypes = [vp, i32, i32]
+        lib.p2s_plan_get_schedule.argtypes = [vp, vp, vp]
+        lib.p2s_plan_autotune.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_char_p, vp]
+        lib.p2s_plan_capture.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.p2s_plan_replay.argtypes = [vp, vp]
         lib.p2s_gauss_rule.argtypes = [i32, vp, vp]
         lib.p2s_linearization.argtypes = [i32, i32, i32, i32, vp]
         for f in ("p2s_create", "p2s_layout", "p2s_plan_create", "p2s_plan_execute",
                   "p2s_fill_element_matrices", "p2s_plan_coupling", "p2s_plan_moments",
-                  "p2s_gauss_rule", "p2s_linearization", "p2s_plan_profile", "p2s_plan_profile_read"):
+                  "p2s_gauss_rule", "p2s_linearization", "p2s_plan_profile", "p2s_plan_profile_read",
+                  "p2s_plan_set_schedule", "p2s_plan_get_schedule", "p2s_plan_autotune", "p2s_plan_capture",
+                  "p2s_plan_replay"):
             getattr(lib, f).restype = i32
         _lib = lib
     return _lib
@@ -215,6 +224,33 @@ class Plan:
         self.ctx.check(load().p2s_plan_profile_read(self._h, _np_ptr(ms), _np_ptr(n)), "p2s_plan_profile_read")
         names = ("coupling", "moments", "contraction", "other")
         return {names[i]: (float(ms[i]), int(n[i])) for i in range(4)}
+
+    def set_schedule(self, mode: int, wgs_per_cu: int = 1):
+        self.ctx.check(load().p2s_plan_set_schedule(self._h, mode, wgs_per_cu), "p2s_plan_set_schedule")
+
+    def schedule(self):
+        m = np.zeros(1, np.int32)
+        w = np.zeros(1, np.int32)
+        self.ctx.check(load().p2s_plan_get_schedule(self._h, _np_ptr(m), _np_ptr(w)), "p2s_plan_get_schedule")
+        return int(m[0]), int(w[0])
+
+    def autotune(self, nodes, material, out, status, cache_path=None, stream=None):
+        """Pick the fastest schedule on these buffers; returns its ms."""
+        best = np.zeros(1)
+        cp = cache_path.encode() if cache_path else None
+        rc = load().p2s_plan_autotune(self._h, _dev_ptr(nodes), _dev_ptr(material), _dev_ptr(out),
+                                      _dev_ptr(status), _stream(stream), cp, _np_ptr(best))
+        self.ctx.check(rc, "p2s_plan_autotune")
+        return float(best[0])
+
+    def capture(self, nodes, material, out, status, stream):
+        """Record one execution into a HIP graph (stream: a torch.cuda.Stream)."""
+        rc = load().p2s_plan_capture(self._h, _dev_ptr(nodes), _dev_ptr(material), _dev_ptr(out),
+                                     _dev_ptr(status), ctypes.c_void_p(stream.cuda_stream))
+        self.ctx.check(rc, "p2s_plan_capture")
+
+    def replay(self, stream=None):
+        self.ctx.check(load().p2s_plan_replay(self._h, _stream(stream)), "p2s_plan_replay")
 
     def coupling(self, nodes, material, stream=None):
         import torch

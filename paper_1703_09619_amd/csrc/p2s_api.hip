@@ -9,7 +9,9 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -30,6 +32,8 @@ struct Chunk {
     int64_t e0 = 0, count = 0;
     // per order class inside the chunk: (N, offset into elist, count)
     std::vector<std::array<int64_t, 3>> classes;
+    // persistent schedule: offset and count of this chunk's work items
+    int64_t item0 = 0, nitem = 0;
 };
 
 struct p2s_plan_s {
@@ -49,6 +53,16 @@ struct p2s_plan_s {
     uint32_t *d_stage_status = nullptr;  // status sink of the stage-output calls
     int64_t alpha_cap = 0, mom_cap = 0;  // doubles
     int64_t bytes = 0;
+    // schedule of the contraction: per-order-class launches (0) or one
+    // persistent launch over a cost-sorted work list (1), with wpc
+    // workgroups per compute unit
+    int mode = 0, wpc = 1;
+    WorkItem *d_items = nullptr;
+    int32_t *d_counter = nullptr;
+    int num_cu = 256;
+    // captured execution
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     // stage timing (events recorded around each launch when enabled)
     bool profile = false;
     std::vector<std::array<hipEvent_t, 2>> ev[4];
@@ -190,6 +204,10 @@ void p2s_plan_destroy(p2s_plan plan)
     hipFree(plan->d_alpha);
     hipFree(plan->d_mom);
     hipFree(plan->d_stage_status);
+    hipFree(plan->d_items);
+    hipFree(plan->d_counter);
+    if (plan->gexec) hipGraphExecDestroy(plan->gexec);
+    if (plan->graph) hipGraphDestroy(plan->graph);
     for (auto &v : plan->ev)
         for (auto &e : v) {
             hipEventDestroy(e[0]);
@@ -206,7 +224,7 @@ static int64_t chunk_budget()
     static int64_t b = -1;
     if (b < 0) {
         const char *s = getenv("P2S_CHUNK_MB");
-        b = (s ? atoll(s) : 512) << 20;
+        b = (s ? atoll(s) : 4096) << 20;
     }
     return b;
 }
@@ -320,6 +338,30 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
             }
         }
     }
+    // work list of the persistent schedule (scalar problem): items sorted by
+    // decreasing cost inside each chunk, items of one element adjacent
+    std::vector<WorkItem> items;
+    if (problem == P2S_SCALAR) {
+        for (auto &c : plan->chunks) {
+            c.item0 = (int64_t)items.size();
+            std::vector<std::pair<int64_t, WorkItem>> v;
+            for (int64_t e = c.e0; e < c.e0 + c.count; ++e) {
+                const int N = orders[e];
+                for (int m1 = 0; m1 < N; ++m1) {
+                    // output written by the item: its rows times the columns m2 >= m1
+                    const int64_t cost = (int64_t)N * N * (N - m1) * N * N;
+                    v.push_back({cost, WorkItem{(int32_t)e, 0, (int16_t)m1}});
+                }
+            }
+            std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+            for (auto &x : v) items.push_back(x.second);
+            c.nitem = (int64_t)items.size() - c.item0;
+        }
+    }
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) plan->num_cu = prop.multiProcessorCount;
+    }
     hipSetDevice(ctx->device);
     bool ok = true;
     if (E > 0) {
@@ -328,15 +370,25 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
         ok = ok && hipMalloc(&plan->d_mom, sizeof(double) * std::max<int64_t>(plan->mom_cap, 1)) == hipSuccess;
         ok = ok && hipMalloc(&plan->d_stage_status, sizeof(uint32_t) * E) == hipSuccess;
         if (!elist.empty()) ok = ok && hipMalloc(&plan->d_elist, sizeof(int32_t) * elist.size()) == hipSuccess;
+        if (!items.empty()) ok = ok && hipMalloc(&plan->d_items, sizeof(WorkItem) * items.size()) == hipSuccess;
+        ok = ok && hipMalloc(&plan->d_counter, sizeof(int32_t)) == hipSuccess;
     }
     if (!ok) {
         p2s_plan_destroy(plan);
         return fail(ctx, P2S_ENOMEM, "plan: workspace allocation failed");
     }
-    plan->bytes = (int64_t)(sizeof(ElemDesc) * E + 8 * (plan->alpha_cap + plan->mom_cap) + 4 * elist.size());
+    plan->bytes = (int64_t)(sizeof(ElemDesc) * E + 8 * (plan->alpha_cap + plan->mom_cap) + 4 * elist.size() +
+                            sizeof(WorkItem) * items.size());
+    // mixed orders of the scalar problem default to the persistent schedule
+    if (!plan->uniform && problem == P2S_SCALAR) {
+        plan->mode = 1;
+        plan->wpc = 1;
+    }
     if (E > 0) {
         if (hipMemcpy(plan->d_desc, desc.data(), sizeof(ElemDesc) * E, hipMemcpyHostToDevice) != hipSuccess ||
             (!elist.empty() && hipMemcpy(plan->d_elist, elist.data(), sizeof(int32_t) * elist.size(),
+                                         hipMemcpyHostToDevice) != hipSuccess) ||
+            (!items.empty() && hipMemcpy(plan->d_items, items.data(), sizeof(WorkItem) * items.size(),
                                          hipMemcpyHostToDevice) != hipSuccess)) {
             p2s_plan_destroy(plan);
             return fail(ctx, P2S_EHIP, "plan: descriptor upload failed");
@@ -382,7 +434,11 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
             continue;
         }
         prof_begin(plan, 2, st);
-        if (plan->uniform) {
+        if (plan->mode == 1) {
+            launch_contract_persistent(problem, plan->d_desc, plan->d_items + c.item0, c.nitem, plan->d_counter,
+                                       plan->num_cu * plan->wpc, ctx->d_tab, plan->d_mom, out, status,
+                                       plan->terms.stiff_scale, plan->terms.mass_scale, st);
+        } else if (plan->uniform) {
             launch_contract(problem, plan->N, plan->d_desc, nullptr, c.e0, c.count, ctx->d_tab,
                             plan->d_mom, out, status, plan->terms.stiff_scale, plan->terms.mass_scale, st);
         } else {
@@ -457,6 +513,185 @@ int p2s_fill_element_matrices(p2s_ctx ctx, const p2s_terms *terms, int64_t E, co
     hipStreamSynchronize((hipStream_t)stream);
     p2s_plan_destroy(plan);
     return r;
+}
+
+int p2s_plan_set_schedule(p2s_plan plan, int mode, int wgs_per_cu)
+{
+    if (!plan) return P2S_EINVAL;
+    if (mode != 0 && mode != 1) return fail(plan->ctx, P2S_EINVAL, "schedule: bad mode %d", mode);
+    if (mode == 1 && plan->terms.problem != P2S_SCALAR)
+        return fail(plan->ctx, P2S_EINVAL, "schedule: the persistent schedule is built for the scalar problem");
+    if (mode == 1 && (wgs_per_cu < 1 || wgs_per_cu > 8))
+        return fail(plan->ctx, P2S_EINVAL, "schedule: workgroups per CU must be 1..8");
+    plan->mode = mode;
+    plan->wpc = mode == 1 ? wgs_per_cu : 1;
+    return P2S_OK;
+}
+
+int p2s_plan_get_schedule(p2s_plan plan, int *mode, int *wgs_per_cu)
+{
+    if (!plan || !mode || !wgs_per_cu) return P2S_EINVAL;
+    *mode = plan->mode;
+    *wgs_per_cu = plan->wpc;
+    return P2S_OK;
+}
+
+// Cache key of a plan shape: problem, order histogram, rule histogram, E.
+static std::string plan_key(p2s_plan plan)
+{
+    std::ostringstream k;
+    k << "gfx950/p" << plan->terms.problem << "/E" << plan->E << "/N";
+    int hist[P2S_MAX_ORDER + 1] = {0};
+    for (int n : plan->orders) hist[n]++;
+    for (int n = 2; n <= P2S_MAX_ORDER; ++n)
+        if (hist[n]) k << n << ":" << hist[n] << ",";
+    std::map<int, int64_t> qh;
+    for (int64_t e = 0; e < plan->E; ++e)
+        qh[plan->quad[3 * e] * 10000 + plan->quad[3 * e + 1] * 100 + plan->quad[3 * e + 2]]++;
+    k << "/Q";
+    uint64_t h = 1469598103934665603ull;  // FNV-1a of the rule histogram
+    for (auto &x : qh) {
+        h = (h ^ (uint64_t)x.first) * 1099511628211ull;
+        h = (h ^ (uint64_t)x.second) * 1099511628211ull;
+    }
+    k << std::hex << h;
+    return k.str();
+}
+
+// Cache file: one JSON object, one entry per line:  "key": [mode, wpc, ms],
+static std::map<std::string, std::array<double, 3>> read_cache(const char *path)
+{
+    std::map<std::string, std::array<double, 3>> m;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t a = line.find('"'), b = line.find('"', a + 1), c = line.find('[', b);
+        if (a == std::string::npos || b == std::string::npos || c == std::string::npos) continue;
+        std::array<double, 3> v{};
+        if (sscanf(line.c_str() + c, "[%lf, %lf, %lf]", &v[0], &v[1], &v[2]) == 3) m[line.substr(a + 1, b - a - 1)] = v;
+    }
+    return m;
+}
+
+static void write_cache(const char *path, const std::map<std::string, std::array<double, 3>> &m)
+{
+    std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp);
+        f.precision(17);
+        f << "{\n";
+        size_t i = 0;
+        for (auto &x : m) {
+            f << "  \"" << x.first << "\": [" << (int)x.second[0] << ", " << (int)x.second[1] << ", "
+              << x.second[2] << "]" << (++i < m.size() ? "," : "") << "\n";
+        }
+        f << "}\n";
+    }
+    std::rename(tmp.c_str(), path);
+}
+
+int p2s_plan_autotune(p2s_plan plan, const double *nodes, const double *material, double *out,
+                      uint32_t *status, void *stream, const char *cache_path, double *best_ms)
+{
+    if (!plan) return P2S_EINVAL;
+    p2s_ctx ctx = plan->ctx;
+    hipStream_t st = (hipStream_t)stream;
+    const std::string key = plan_key(plan);
+    if (cache_path) {
+        auto m = read_cache(cache_path);
+        auto it = m.find(key);
+        if (it != m.end()) {
+            int r = p2s_plan_set_schedule(plan, (int)it->second[0], (int)it->second[1]);
+            if (r == P2S_OK) {
+                if (best_ms) *best_ms = it->second[2];
+                return P2S_OK;
+            }
+        }
+    }
+    std::vector<std::array<int, 2>> cand = {{0, 1}};
+    if (plan->terms.problem == P2S_SCALAR) {
+        cand.push_back({1, 1});
+        cand.push_back({1, 2});
+        cand.push_back({1, 4});
+    }
+    const bool prof = plan->profile;
+    plan->profile = false;
+    hipEvent_t t0, t1;
+    HIP_TRY(ctx, hipEventCreate(&t0));
+    HIP_TRY(ctx, hipEventCreate(&t1));
+    double best = 1e300;
+    std::array<int, 2> pick = {plan->mode, plan->wpc};
+    int rc = P2S_OK;
+    for (auto &c : cand) {
+        plan->mode = c[0];
+        plan->wpc = c[1];
+        if ((rc = run_plan(plan, nodes, material, out, status, st, STOP_FULL, nullptr)) != P2S_OK) break;
+        hipEventRecord(t0, st);
+        const int reps = 3;
+        for (int r = 0; r < reps && rc == P2S_OK; ++r) rc = run_plan(plan, nodes, material, out, status, st, STOP_FULL, nullptr);
+        hipEventRecord(t1, st);
+        if (rc != P2S_OK) break;
+        hipEventSynchronize(t1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, t0, t1);
+        if (ms / reps < best) {
+            best = ms / reps;
+            pick = c;
+        }
+    }
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    plan->profile = prof;
+    plan->mode = pick[0];
+    plan->wpc = pick[1];
+    if (rc != P2S_OK) return rc;
+    if (best_ms) *best_ms = best;
+    if (cache_path) {
+        auto m = read_cache(cache_path);
+        m[key] = {(double)pick[0], (double)pick[1], best};
+        write_cache(cache_path, m);
+    }
+    return P2S_OK;
+}
+
+int p2s_plan_capture(p2s_plan plan, const double *nodes, const double *material, double *out,
+                     uint32_t *status, void *stream)
+{
+    if (!plan) return P2S_EINVAL;
+    p2s_ctx ctx = plan->ctx;
+    hipStream_t st = (hipStream_t)stream;
+    if (!st) return fail(ctx, P2S_EINVAL, "capture: needs a non-default stream");
+    if (plan->gexec) {
+        hipGraphExecDestroy(plan->gexec);
+        plan->gexec = nullptr;
+    }
+    if (plan->graph) {
+        hipGraphDestroy(plan->graph);
+        plan->graph = nullptr;
+    }
+    const bool prof = plan->profile;
+    plan->profile = false;  // no event records inside the graph
+    HIP_TRY(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int r = run_plan(plan, nodes, material, out, status, st, STOP_FULL, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    plan->profile = prof;
+    if (r != P2S_OK) {
+        if (g) hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return fail(ctx, P2S_EHIP, "capture: %s", hipGetErrorString(e));
+    plan->graph = g;
+    HIP_TRY(ctx, hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0));
+    return P2S_OK;
+}
+
+int p2s_plan_replay(p2s_plan plan, void *stream)
+{
+    if (!plan) return P2S_EINVAL;
+    if (!plan->gexec) return fail(plan->ctx, P2S_EINVAL, "replay: no captured execution");
+    HIP_TRY(plan->ctx, hipGraphLaunch(plan->gexec, (hipStream_t)stream));
+    return P2S_OK;
 }
 
 }  // extern "C"

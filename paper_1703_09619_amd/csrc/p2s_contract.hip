@@ -276,26 +276,23 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t total_padded)
     return (w & 7) * per + (w >> 3);
 }
 
+// One work item: rows (m1, n1, p1) of component I of element e against the
+// column components J >= I.  Called by all `nthreads` threads of a
+// workgroup (nthreads >= THREADS; extra threads take part in the barriers
+// and the cooperative loops only).  smem holds at least BUF doubles.
 template <int PROB, int N, int I>
-__global__ __launch_bounds__((CS<PROB, N, I>::THREADS)) void k_contract(
-    const ElemDesc *__restrict__ desc, const int32_t *__restrict__ elist, int64_t e0, int64_t nitems,
-    int64_t padded, const double *__restrict__ tab, const double *__restrict__ mom,
-    double *__restrict__ out, uint32_t *__restrict__ status, double sK, double sM)
+__device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int m1,
+                                              const double *__restrict__ tab, const double *__restrict__ mom,
+                                              double *__restrict__ out, uint32_t *__restrict__ status,
+                                              double sK, double sM, double *__restrict__ smem, int nthreads)
 {
     using S = CS<PROB, N, I>;
     constexpr int K = S::K, KS = S::KS, NC = S::NC, NDOF = S::NDOF, G = S::G;
     constexpr int NN_I = S::NN_I, NP_I = S::NP_I;
-    const int64_t item = xcd_remap(blockIdx.x, padded);
-    if (item >= nitems) return;
-    const int64_t eidx = e0 + item / S::NM_I;
-    const int64_t e = elist ? (int64_t)elist[eidx] : eidx;
-    const int m1 = (int)(item % S::NM_I);
-    const ElemDesc d = desc[e];
     const double *lin = tab + TAB_LIN;
     const double *pack = tab + TAB_PACK;
     const double *I0 = mom + d.mom_off;
     double *obase = out + d.out_off;
-    __shared__ __attribute__((aligned(16))) double smem[S::BUF];
     const int tid = threadIdx.x;
     const int rowbase = comp_offset(PROB, N, I) + m1 * NN_I * NP_I;
     bool bad = false;
@@ -329,7 +326,7 @@ __global__ __launch_bounds__((CS<PROB, N, I>::THREADS)) void k_contract(
             double *Abuf = smem;                    // [ng][N][K][KS]
             double *Cbuf = smem + ng * S::A_DOUBLES;  // [ng][NN_I*NN_J][KS]
             // stage-B coefficient rows of this batch into LDS
-            for (int x = tid; x < ng * NN_I * NN_J * K; x += S::THREADS) {
+            for (int x = tid; x < ng * NN_I * NN_J * K; x += nthreads) {
                 const int gl = x / (NN_I * NN_J * K);
                 const int r = x - gl * (NN_I * NN_J * K);
                 const int nn = r / K, l = r - (r / K) * K;
@@ -343,7 +340,7 @@ __global__ __launch_bounds__((CS<PROB, N, I>::THREADS)) void k_contract(
                     lin[tv * LIN_STRIDE_T + a1 * LIN_STRIDE_M1 + a2 * KPAD + l];
             }
             // stage A: worker w -> (group gl, entry lq); gl is wave-uniform
-            for (int w = tid; w < ng * S::SA; w += S::THREADS) {
+            for (int w = tid; w < ng * S::SA; w += nthreads) {
                 const int gl = w / S::SA;
                 const int lq = w - gl * S::SA;
                 if (lq < K * K) {
@@ -447,13 +444,13 @@ __global__ __launch_bounds__((CS<PROB, N, I>::THREADS)) void k_contract(
                                  ((reinterpret_cast<uintptr_t>(drow) & 15u) == 0);
                 if (d16) {
                     const int hw = W / 2;
-                    for (int x = tid; x < nr * hw; x += S::THREADS) {
+                    for (int x = tid; x < nr * hw; x += nthreads) {
                         const int r = x / hw, c = 2 * (x - r * hw);
                         *reinterpret_cast<double2 *>(drow + (int64_t)r * NDOF + c) =
                             *reinterpret_cast<const double2 *>(smem + r * WS + c);
                     }
                 } else {
-                    for (int x = tid; x < nr * W; x += S::THREADS) {
+                    for (int x = tid; x < nr * W; x += nthreads) {
                         const int r = x / W, c = x - r * W;
                         drow[(int64_t)r * NDOF + c] = smem[r * WS + c];
                     }
@@ -466,13 +463,13 @@ __global__ __launch_bounds__((CS<PROB, N, I>::THREADS)) void k_contract(
                                  ((reinterpret_cast<uintptr_t>(mrow) & 15u) == 0);
                 if (m16) {
                     const int hr = nr / 2;
-                    for (int x = tid; x < nc * hr; x += S::THREADS) {
+                    for (int x = tid; x < nc * hr; x += nthreads) {
                         const int c = cmir + x / hr, r = 2 * (x - (x / hr) * hr);
                         *reinterpret_cast<double2 *>(mrow + (int64_t)c * NDOF + r) =
                             make_double2(smem[r * WS + c], smem[(r + 1) * WS + c]);
                     }
                 } else {
-                    for (int x = tid; x < nc * nr; x += S::THREADS) {
+                    for (int x = tid; x < nc * nr; x += nthreads) {
                         const int c = cmir + x / nr, r = x - (x / nr) * nr;
                         mrow[(int64_t)c * NDOF + r] = smem[r * WS + c];
                     }
@@ -485,6 +482,23 @@ __global__ __launch_bounds__((CS<PROB, N, I>::THREADS)) void k_contract(
 }
 
 template <int PROB, int N, int I>
+__global__ __launch_bounds__((CS<PROB, N, I>::THREADS)) void k_contract(
+    const ElemDesc *__restrict__ desc, const int32_t *__restrict__ elist, int64_t e0, int64_t nitems,
+    int64_t padded, const double *__restrict__ tab, const double *__restrict__ mom,
+    double *__restrict__ out, uint32_t *__restrict__ status, double sK, double sM)
+{
+    using S = CS<PROB, N, I>;
+    const int64_t item = xcd_remap(blockIdx.x, padded);
+    if (item >= nitems) return;
+    const int64_t eidx = e0 + item / S::NM_I;
+    const int64_t e = elist ? (int64_t)elist[eidx] : eidx;
+    const int m1 = (int)(item % S::NM_I);
+    const ElemDesc d = desc[e];
+    __shared__ __attribute__((aligned(16))) double smem[S::BUF];
+    contract_item<PROB, N, I>(d, e, m1, tab, mom, out, status, sK, sM, smem, S::THREADS);
+}
+
+template <int PROB, int N, int I>
 static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,
                               const double *tab, const double *mom, double *out, uint32_t *status,
                               double sK, double sM, hipStream_t st)
@@ -494,6 +508,77 @@ static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_
     const int64_t padded = (nitems + 7) / 8 * 8;
     hipLaunchKernelGGL((k_contract<PROB, N, I>), dim3((unsigned)padded), dim3(S::THREADS), 0, st, desc,
                        elist, e0, nitems, padded, tab, mom, out, status, sK, sM);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent schedule for batches of mixed orders: one launch of a fixed
+// grid; every workgroup takes the next work item (element, component, m1)
+// from a list sorted by decreasing cost (longest-processing-time first)
+// through an atomic counter, and leaves when the list is exhausted.
+
+template <int PROB>
+struct PersistentShape {
+    static constexpr int threads()
+    {
+        int m = 0;
+        m = cmax(m, CS<PROB, 2, 0>::THREADS); m = cmax(m, CS<PROB, 3, 0>::THREADS);
+        m = cmax(m, CS<PROB, 4, 0>::THREADS); m = cmax(m, CS<PROB, 5, 0>::THREADS);
+        m = cmax(m, CS<PROB, 6, 0>::THREADS); m = cmax(m, CS<PROB, 7, 0>::THREADS);
+        m = cmax(m, CS<PROB, 8, 0>::THREADS);
+        return m;
+    }
+    static constexpr int buf()
+    {
+        int m = 0;
+        m = cmax(m, CS<PROB, 2, 0>::BUF); m = cmax(m, CS<PROB, 3, 0>::BUF);
+        m = cmax(m, CS<PROB, 4, 0>::BUF); m = cmax(m, CS<PROB, 5, 0>::BUF);
+        m = cmax(m, CS<PROB, 6, 0>::BUF); m = cmax(m, CS<PROB, 7, 0>::BUF);
+        m = cmax(m, CS<PROB, 8, 0>::BUF);
+        return m;
+    }
+    static constexpr int THREADS = threads();
+    static constexpr int BUF = buf();
+};
+
+__global__ void k_reset_counter(int32_t *counter) { *counter = 0; }
+
+__global__ __launch_bounds__(PersistentShape<0>::THREADS) void k_contract_persistent_scalar(
+    const ElemDesc *__restrict__ desc, const WorkItem *__restrict__ items, int32_t nitems,
+    int32_t *__restrict__ counter, const double *__restrict__ tab, const double *__restrict__ mom,
+    double *__restrict__ out, uint32_t *__restrict__ status, double sK, double sM)
+{
+    __shared__ __attribute__((aligned(16))) double smem[PersistentShape<0>::BUF];
+    __shared__ int32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t it = next;
+        __syncthreads();  // every thread has read `next` before it is overwritten
+        if (it >= nitems) break;
+        const WorkItem w = items[it];
+        const ElemDesc d = desc[w.e];
+        switch (d.N) {
+        case 2: contract_item<0, 2, 0>(d, w.e, w.m1, tab, mom, out, status, sK, sM, smem, blockDim.x); break;
+        case 3: contract_item<0, 3, 0>(d, w.e, w.m1, tab, mom, out, status, sK, sM, smem, blockDim.x); break;
+        case 4: contract_item<0, 4, 0>(d, w.e, w.m1, tab, mom, out, status, sK, sM, smem, blockDim.x); break;
+        case 5: contract_item<0, 5, 0>(d, w.e, w.m1, tab, mom, out, status, sK, sM, smem, blockDim.x); break;
+        case 6: contract_item<0, 6, 0>(d, w.e, w.m1, tab, mom, out, status, sK, sM, smem, blockDim.x); break;
+        case 7: contract_item<0, 7, 0>(d, w.e, w.m1, tab, mom, out, status, sK, sM, smem, blockDim.x); break;
+        default: contract_item<0, 8, 0>(d, w.e, w.m1, tab, mom, out, status, sK, sM, smem, blockDim.x); break;
+        }
+    }
+}
+
+int launch_contract_persistent(int problem, const ElemDesc *desc, const WorkItem *items, int64_t nitems,
+                               int32_t *counter, int grid, const double *tab, const double *mom, double *out,
+                               uint32_t *status, double sK, double sM, hipStream_t st)
+{
+    if (problem != 0) return -1;
+    if (nitems <= 0) return 0;
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, counter);
+    hipLaunchKernelGGL(k_contract_persistent_scalar, dim3(grid), dim3(PersistentShape<0>::THREADS), 0, st,
+                       desc, items, (int32_t)nitems, counter, tab, mom, out, status, sK, sM);
+    return 0;
 }
 
 template <int PROB, int N>

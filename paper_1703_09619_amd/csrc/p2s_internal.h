@@ -107,6 +107,13 @@ constexpr uint32_t P2S_STATUS_NONFINITE_BIT = 2u;
 constexpr uint32_t P2S_STATUS_FALLBACK_BIT = 4u;
 constexpr uint32_t P2S_STATUS_TAIL_BIT = 8u;
 
+// Work item of the persistent contraction: rows (m1, ., .) of component
+// `comp` of element e.
+struct WorkItem {
+    int32_t e;
+    int16_t comp, m1;
+};
+
 // Per-element descriptor used by every kernel.
 struct ElemDesc {
     int32_t N, Qu, Qv, Qw;

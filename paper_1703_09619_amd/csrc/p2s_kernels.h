@@ -22,4 +22,9 @@ int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *eli
                     int64_t count, const double *tab, const double *mom, double *out, uint32_t *status,
                     double sK, double sM, hipStream_t st);
 
+// One launch over a cost-sorted work list (scalar problem, mixed orders).
+int launch_contract_persistent(int problem, const ElemDesc *desc, const WorkItem *items, int64_t nitems,
+                               int32_t *counter, int grid, const double *tab, const double *mom, double *out,
+                               uint32_t *status, double sK, double sM, hipStream_t st);
+
 }  // namespace p2s

@@ -230,3 +230,75 @@ def test_vector_n6_full_size_sampled(env):
         err = np.linalg.norm(x - y) / np.linalg.norm(y)
         print("element", e, "rel err %.3e" % err, flush=True)
         assert err <= TOL
+
+
+def test_persistent_schedule_matches_per_class(env):
+    """Mixed orders: the persistent launch over the cost-sorted work list
+    and the per-order-class launches give bit-identical matrices."""
+    torch, W = env["torch"], env["W"]
+    w = W.make("scalar_mixed", E=300)
+    plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
+    assert plan.schedule()[0] == 1
+    nodes = torch.from_numpy(w.nodes).cuda()
+    mat = torch.from_numpy(w.mat).cuda()
+    a, sa = plan.execute(nodes, mat)
+    plan.set_schedule(0)
+    b, sb = plan.execute(nodes, mat)
+    plan.set_schedule(1, 3)
+    c, _ = plan.execute(nodes, mat)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c) and torch.equal(sa, sb)
+    with pytest.raises(env["p2s"].P2SError):
+        env["ctx"].plan(1, 1, [4], [[4, 4, 4]]).set_schedule(1, 1)
+
+
+def test_autotune_and_cache(env, tmp_path):
+    torch, W = env["torch"], env["W"]
+    w = W.make("scalar_mixed", E=200)
+    plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
+    nodes = torch.from_numpy(w.nodes).cuda()
+    mat = torch.from_numpy(w.mat).cuda()
+    out = torch.empty(int(plan.offsets[-1]), dtype=torch.float64, device="cuda")
+    st = torch.empty(w.E, dtype=torch.int32, device="cuda")
+    cache = str(tmp_path / "tune.json")
+    ms = plan.autotune(nodes, mat, out, st, cache)
+    assert ms > 0
+    choice = plan.schedule()
+    import json
+    entries = json.load(open(cache))
+    assert len(entries) == 1
+    plan2 = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
+    ms2 = plan2.autotune(nodes, mat, out, st, cache)
+    assert plan2.schedule() == choice and abs(ms2 - ms) <= 1e-12 * ms
+    ref, roff, _ = env["oracle"].fill(w.problem, w.material, w.nodes[:3], w.mat[:3], w.orders[:3], w.quad[:3])
+    plan2.execute(nodes, mat, out, st)
+    torch.cuda.synchronize()
+    g = out[:int(roff[-1])].cpu().numpy()
+    assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name,E", [("scalar_mixed", 150), ("vector_n6", 40)])
+def test_graph_replay(env, name, E):
+    """Captured execution replayed several times, with eager work and
+    synchronizations between replays; every replay equals the eager fill."""
+    torch, W = env["torch"], env["W"]
+    w = W.make(name, E=E)
+    plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
+    nodes = torch.from_numpy(w.nodes).cuda()
+    mat = torch.from_numpy(w.mat).cuda()
+    ref, rst = plan.execute(nodes, mat)
+    torch.cuda.synchronize()
+    out = torch.empty_like(ref)
+    st = torch.empty_like(rst)
+    s = torch.cuda.Stream()
+    plan.capture(nodes, mat, out, st, s)
+    for k in range(4):
+        out.fill_(float("nan"))
+        st.fill_(-1)
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        plan.replay(s)
+        s.synchronize()
+        assert torch.equal(out, ref), k
+        assert torch.equal(st, rst), k
+        float(junk)
