@@ -60,6 +60,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="vector_n6", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--direct-elements", type=int, default=64,
+                    help="elements of the same workload filled by the GPU direct-quadrature baseline "
+                         "(0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="before the fill, run a plain 1 GiB device copy three times (a known-size "
                          "reference for HBM byte counters)")
@@ -130,6 +133,30 @@ def main():
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "status_nonzero": int((st != 0).sum()),
     }
+
+    if args.direct_elements > 0 and len(set(w.orders.tolist())) == 1:
+        # the method the paper compares against, on the GPU: direct quadrature
+        # of every entry (same inputs, first elements of the batch)
+        sub = W.subset(w, np.arange(min(args.direct_elements, w.E)))
+        dplan = ctx.plan(sub.problem, sub.material, sub.orders, sub.quad, method=p2s.METHOD_DIRECT)
+        dn = torch.from_numpy(sub.nodes).to(dev)
+        dm = torch.from_numpy(sub.mat).to(dev)
+        dout = torch.empty(int(dplan.offsets[-1]), dtype=torch.float64, device=dev)
+        dst = torch.empty(sub.E, dtype=torch.int32, device=dev)
+        dplan.execute(dn, dm, dout, dst)
+        torch.cuda.synchronize()
+        d0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            dplan.execute(dn, dm, dout, dst)
+        torch.cuda.synchronize()
+        d1 = time.perf_counter()
+        ref = out[:int(dplan.offsets[-1])]
+        derr = float(((dout - ref).norm() / ref.norm()).item())
+        result["gpu_direct_quadrature"] = {
+            "value": round(sub.E * reps / (d1 - d0), 1), "unit": "element matrices/s", "elements": sub.E,
+            "rel_frobenius_diff_vs_p2s": derr}
+        del dout
 
     if not args.no_cpu_baseline:
         import oracle

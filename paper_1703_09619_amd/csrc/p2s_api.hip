@@ -249,8 +249,10 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
     }
     if (problem == P2S_SCALAR && kind == P2S_MAT_ROTDIAG)
         return fail(ctx, P2S_EINVAL, "plan: the scalar problem takes an isotropic material");
-    if (terms->precision != P2S_FP64 || terms->method != P2S_METHOD_P2S)
-        return fail(ctx, P2S_EINVAL, "plan: unsupported precision/method combination");
+    if (terms->method != P2S_METHOD_P2S && terms->method != P2S_METHOD_DIRECT)
+        return fail(ctx, P2S_EINVAL, "plan: bad method %d", terms->method);
+    if (terms->precision != P2S_FP64)
+        return fail(ctx, P2S_EINVAL, "plan: unsupported precision %d", terms->precision);
     auto plan = new p2s_plan_s();
     plan->ctx = ctx;
     plan->terms = *terms;
@@ -286,6 +288,10 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
         plan->Qu = quad[0];
         plan->Qv = quad[1];
         plan->Qw = quad[2];
+    }
+    if (terms->method == P2S_METHOD_DIRECT && !plan->uniform) {
+        delete plan;
+        return fail(ctx, P2S_EINVAL, "plan: direct quadrature takes one order and rule for all elements");
     }
     if (kind == P2S_ALPHA_SAMPLED && !plan->uniform) {
         delete plan;
@@ -416,6 +422,13 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         launch_coupling(problem, plan->d_desc, c.e0, c.count, nodes, material, plan->terms.material,
                         plan->mat_stride, ctx->d_tab, plan->d_alpha, status, st);
         prof_end(plan, 0, st);
+        if (plan->terms.method == P2S_METHOD_DIRECT && stop == STOP_FULL) {
+            prof_begin(plan, 3, st);
+            launch_direct(problem, plan->N, plan->d_desc, c.e0, c.count, ctx->d_tab, plan->d_alpha, out,
+                          plan->terms.stiff_scale, plan->terms.mass_scale, st);
+            prof_end(plan, 3, st);
+            continue;
+        }
         if (stop == STOP_COUPLING) {
             const int64_t per = (int64_t)F * plan->Qu * plan->Qv * plan->Qw;
             HIP_TRY(ctx, hipMemcpyAsync(stage_out + c.e0 * per, plan->d_alpha, sizeof(double) * per * c.count,

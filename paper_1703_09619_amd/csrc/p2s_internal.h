@@ -98,7 +98,11 @@ constexpr int TAB_GX = TAB_LIN + LIN_SIZE;
 constexpr int TAB_GW = TAB_GX + GX_SIZE;
 constexpr int TAB_LEGW = TAB_GW + GX_SIZE;
 constexpr int TAB_PACK = TAB_LEGW + LEGW_SIZE;
-constexpr int TAB_SIZE = TAB_PACK + PACKED_SIZE;
+// 1-D basis values at the Gauss points (direct quadrature):
+// basis[Q][family][m][a] for family in {phi, phi', psi}
+constexpr int BASIS_STRIDE_Q = NFAM * MAXN * MAXQ;
+constexpr int TAB_BASIS = TAB_PACK + PACKED_SIZE;
+constexpr int TAB_SIZE = TAB_BASIS + (MAXQ + 1) * BASIS_STRIDE_Q;
 
 // Mirrors of the public enums and status bits (include/p2s.h).
 enum MatKind : int { MAT_SINCOSEXP = 0, MAT_ROTDIAG = 1, MAT_PLANEWAVE = 2, ALPHA_SAMPLED = 3 };

@@ -27,4 +27,8 @@ int launch_contract_persistent(int problem, const ElemDesc *desc, const WorkItem
                                int32_t *counter, int grid, const double *tab, const double *mom, double *out,
                                uint32_t *status, double sK, double sM, hipStream_t st);
 
+// Direct quadrature of eq. (2) (baseline method), from coupling samples.
+void launch_direct(int problem, int N, const ElemDesc *desc, int64_t e0, int64_t count, const double *tab,
+                   const double *alpha, double *out, double sK, double sM, hipStream_t st);
+
 }  // namespace p2s

@@ -139,6 +139,17 @@ void build_tables(double *tab)
         double *x = tab + TAB_GX + Q * MAXQ;
         double *w = tab + TAB_GW + Q * MAXQ;
         gauss_rule(Q, x, w);
+        // basis values at the points from the Legendre expansions
+        for (int a = 0; a < Q; ++a) {
+            legendre_values(KPAD - 1, x[a], L);
+            for (int fam = 0; fam < NFAM; ++fam)
+                for (int m = 0; m < MAXN; ++m) {
+                    double c[KPAD], v = 0.0;
+                    family_coefficients(fam, m, c);
+                    for (int k = 0; k < KPAD; ++k) v += c[k] * L[k];
+                    tab[TAB_BASIS + Q * BASIS_STRIDE_Q + (fam * MAXN + m) * MAXQ + a] = v;
+                }
+        }
         for (int a = 0; a < Q; ++a) {
             legendre_values(KPAD - 1, x[a], L);
             for (int k = 0; k < KPAD; ++k)

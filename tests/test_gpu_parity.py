@@ -47,10 +47,10 @@ def rel_errors(a, b, off):
     return np.array(errs)
 
 
-def check_against_oracle(env, w, sK=1.0, sM=1.0, tol=TOL):
+def check_against_oracle(env, w, sK=1.0, sM=1.0, tol=TOL, method=0):
     print("case", w.get("name"), "E", w["E"], "orders", sorted(set(np.asarray(w["orders"]).tolist())),
-          "quad0", np.asarray(w["quad"])[0].tolist(), flush=True)
-    out, off, st, _ = gpu_fill(env, w, stiff_scale=sK, mass_scale=sM)
+          "quad0", np.asarray(w["quad"])[0].tolist(), "method", method, flush=True)
+    out, off, st, _ = gpu_fill(env, w, stiff_scale=sK, mass_scale=sM, method=method)
     ref, roff, rst = env["oracle"].fill(w["problem"], w["material"], w["nodes"], w["mat"],
                                         w["orders"], w["quad"], sK, sM)
     assert np.array_equal(off, roff)
@@ -302,3 +302,11 @@ def test_graph_replay(env, name, E):
         assert torch.equal(out, ref), k
         assert torch.equal(st, rst), k
         float(junk)
+
+
+@pytest.mark.parametrize("problem,N,Q", [(0, 4, (8, 8, 8)), (0, 5, (6, 7, 8)), (1, 3, (5, 5, 5)),
+                                         (1, 4, (6, 5, 7)), (1, 6, (12, 12, 12))])
+def test_direct_quadrature_method(env, problem, N, Q):
+    """The GPU direct-quadrature baseline (eq. (2) without eq. (3))."""
+    w = make_small(env, problem, N, 2, Q, seed=300 + N)
+    check_against_oracle(env, w, method=1)
