@@ -182,6 +182,71 @@ int p2s_plan_capture(p2s_plan plan, const double *nodes, const double *material,
                      uint32_t *status, void *stream);
 int p2s_plan_replay(p2s_plan plan, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned quadrature order.  A network (FP32, 85 -> 128 -> 128 -> 57, ReLU)
+ * maps an element's features to a distribution, per axis, over the Gauss
+ * rule size K in {P2S_KMIN..P2S_KMAX} used to sample the coupling factor
+ * for the moment stage.  Features [E][85] (FP32): the 81 node offsets from
+ * the nominal unit cube divided by 0.3, then four material parameters
+ * (plane wave: |k_x|, |k_y|, |k_z| / (16 pi), phase / (2 pi) - 1/2).  Logits [B][57]:
+ * axis a's 19 classes at [a*19 .. a*19+18], class c <-> K = P2S_KMIN + c.
+ * The parameters live in the context. */
+#define P2S_MLP_IN 85
+#define P2S_MLP_HIDDEN 128
+#define P2S_MLP_OUT 57
+#define P2S_MLP_PARAMS 34873
+#define P2S_KMIN 6
+#define P2S_KMAX 24
+
+/* Initialise the parameters (He-normal weights from `seed`, zero biases),
+ * reset Adam, and size the training scratch for batches up to max_batch. */
+int p2s_mlp_init(p2s_ctx ctx, uint64_t seed, int64_t max_batch);
+/* Parameters [host][P2S_MLP_PARAMS]: W1 [85][128], b1 [128], W2 [128][128],
+ * b2 [128], W3 [128][57], b3 [57] (weights input-major). */
+int p2s_mlp_set_params(p2s_ctx ctx, const float *params);
+int p2s_mlp_get_params(p2s_ctx ctx, float *params);
+/* Binary file: "P2SK", int32 version 1, int32 (85, 128, 57), float32 params. */
+int p2s_mlp_save(p2s_ctx ctx, const char *path);
+int p2s_mlp_load(p2s_ctx ctx, const char *path);
+/* Features of E elements: nodes, material [device] as in p2s_plan_execute,
+ * x [device][E][85]. */
+int p2s_features(p2s_ctx ctx, int material, int64_t E, const double *nodes, const double *mat, float *x,
+                 void *stream);
+/* Forward pass, x [device][B][85] -> logits [device][B][57], B <= max_batch. */
+int p2s_mlp_forward(p2s_ctx ctx, int64_t B, const float *x, float *logits, void *stream);
+/* Mean-over-batch softmax cross-entropy (summed over the three axes) with
+ * class labels [device][B][3]: loss [device] (one float, the batch SUM of
+ * per-sample losses), gradient [device][P2S_MLP_PARAMS] of the mean loss
+ * (grad may be NULL).  p2s_mlp_train_step does the same and applies one
+ * Adam step (beta 0.9/0.999, eps 1e-8) with learning rate lr. */
+int p2s_mlp_gradients(p2s_ctx ctx, int64_t B, const float *x, const int32_t *labels, float *grad, float *loss,
+                      void *stream);
+int p2s_mlp_train_step(p2s_ctx ctx, int64_t B, const float *x, const int32_t *labels, float lr, float *loss,
+                       void *stream);
+/* Per-axis rule: the smallest K whose predicted cumulative probability
+ * reaches p_cover; quad [device][B][3]. */
+int p2s_mlp_predict(p2s_ctx ctx, int64_t B, const float *x, float p_cover, int32_t *quad, void *stream);
+/* Learned mode of a plan created with P2S_KMAX points on every axis (so its
+ * workspace holds the full rule): each execution computes the features,
+ * runs the network, samples the coupling factor with the chosen rules,
+ * and checks the tail: along each axis the Legendre coefficients of the two
+ * highest degrees the rule resolves, over all lines of points and fields,
+ * relative to the largest coupling value; above theta the element is
+ * sampled again with the full rule (status P2S_STATUS_FALLBACK; still above
+ * theta afterwards: P2S_STATUS_TAIL).  Allocates its workspace here;
+ * enable = 0 restores the plan's own rules. */
+int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, double theta);
+/* Rules used by the last execution: quad [host][E][3]. */
+int p2s_plan_rules(p2s_plan plan, int32_t *quad);
+/* Tail statistic of each element at its predicted rule in the last learned
+ * execution: tau [host][E] (synchronizes the device). */
+int p2s_plan_tail_values(p2s_plan plan, double *tau);
+/* Per-element relative Frobenius difference ||a - b||_F / ||b||_F of blocks
+ * [device] at offsets [device][E+1] (or of E blocks of len doubles when
+ * offsets is NULL); err [device][E]. */
+int p2s_rel_error(p2s_ctx ctx, int64_t E, int64_t len, const int64_t *offsets, const double *a, const double *b,
+                  double *err, void *stream);
+
 /* One-shot fill: plan create + execute + destroy (the plan is destroyed
  * after the stream has finished the work, so this call synchronizes the
  * stream).  Arguments as above. */

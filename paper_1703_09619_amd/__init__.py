@@ -34,8 +34,12 @@ EXPORTS = (
     "p2s_fill_element_matrices", "p2s_plan_coupling", "p2s_plan_moments",
     "p2s_gauss_rule", "p2s_linearization", "p2s_plan_profile", "p2s_plan_profile_read",
     "p2s_plan_set_schedule", "p2s_plan_get_schedule", "p2s_plan_autotune", "p2s_plan_capture",
-    "p2s_plan_replay",
+    "p2s_plan_replay", "p2s_mlp_init", "p2s_mlp_set_params", "p2s_mlp_get_params", "p2s_mlp_save",
+    "p2s_mlp_load", "p2s_features", "p2s_mlp_forward", "p2s_mlp_gradients", "p2s_mlp_train_step",
+    "p2s_mlp_predict", "p2s_plan_set_learned", "p2s_plan_rules", "p2s_rel_error", "p2s_plan_tail_values",
 )
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 85, 128, 57, 34873
+KMIN, KMAX = 6, 24
 
 
 class P2SError(RuntimeError):
@@ -83,13 +87,30 @@ def load():
         lib.p2s_plan_autotune.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_char_p, vp]
         lib.p2s_plan_capture.argtypes = [vp, vp, vp, vp, vp, vp]
         lib.p2s_plan_replay.argtypes = [vp, vp]
+        lib.p2s_mlp_init.argtypes = [vp, ctypes.c_uint64, i64]
+        lib.p2s_mlp_set_params.argtypes = [vp, vp]
+        lib.p2s_mlp_get_params.argtypes = [vp, vp]
+        lib.p2s_mlp_save.argtypes = [vp, ctypes.c_char_p]
+        lib.p2s_mlp_load.argtypes = [vp, ctypes.c_char_p]
+        lib.p2s_features.argtypes = [vp, i32, i64, vp, vp, vp, vp]
+        lib.p2s_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
+        lib.p2s_mlp_gradients.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        lib.p2s_mlp_train_step.argtypes = [vp, i64, vp, vp, ctypes.c_float, vp, vp]
+        lib.p2s_mlp_predict.argtypes = [vp, i64, vp, ctypes.c_float, vp, vp]
+        lib.p2s_plan_set_learned.argtypes = [vp, i32, ctypes.c_float, d]
+        lib.p2s_plan_rules.argtypes = [vp, vp]
+        lib.p2s_plan_tail_values.argtypes = [vp, vp]
+        lib.p2s_rel_error.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
         lib.p2s_gauss_rule.argtypes = [i32, vp, vp]
         lib.p2s_linearization.argtypes = [i32, i32, i32, i32, vp]
         for f in ("p2s_create", "p2s_layout", "p2s_plan_create", "p2s_plan_execute",
                   "p2s_fill_element_matrices", "p2s_plan_coupling", "p2s_plan_moments",
                   "p2s_gauss_rule", "p2s_linearization", "p2s_plan_profile", "p2s_plan_profile_read",
                   "p2s_plan_set_schedule", "p2s_plan_get_schedule", "p2s_plan_autotune", "p2s_plan_capture",
-                  "p2s_plan_replay"):
+                  "p2s_plan_replay", "p2s_mlp_init", "p2s_mlp_set_params", "p2s_mlp_get_params",
+                  "p2s_mlp_save", "p2s_mlp_load", "p2s_features", "p2s_mlp_forward", "p2s_mlp_gradients",
+                  "p2s_mlp_train_step", "p2s_mlp_predict", "p2s_plan_set_learned", "p2s_plan_rules",
+                  "p2s_rel_error", "p2s_plan_tail_values"):
             getattr(lib, f).restype = i32
         _lib = lib
     return _lib
@@ -174,6 +195,70 @@ class Context:
         except Exception:
             pass
 
+    # ---- learned quadrature order (network held by the context)
+    def mlp_init(self, seed: int = 0, max_batch: int = 4096):
+        self.check(load().p2s_mlp_init(self._h, seed, max_batch), "p2s_mlp_init")
+
+    def mlp_params(self) -> np.ndarray:
+        p = np.zeros(MLP_PARAMS, np.float32)
+        self.check(load().p2s_mlp_get_params(self._h, _np_ptr(p)), "p2s_mlp_get_params")
+        return p
+
+    def mlp_set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == MLP_PARAMS
+        self.check(load().p2s_mlp_set_params(self._h, _np_ptr(p)), "p2s_mlp_set_params")
+
+    def mlp_save(self, path: str):
+        self.check(load().p2s_mlp_save(self._h, path.encode()), "p2s_mlp_save")
+
+    def mlp_load(self, path: str):
+        self.check(load().p2s_mlp_load(self._h, path.encode()), "p2s_mlp_load")
+
+    def features(self, material, nodes, mat, stream=None):
+        import torch
+        E = nodes.shape[0]
+        x = torch.empty((E, MLP_IN), dtype=torch.float32, device=nodes.device)
+        self.check(load().p2s_features(self._h, material, E, _dev_ptr(nodes), _dev_ptr(mat), _dev_ptr(x),
+                                       _stream(stream)), "p2s_features")
+        return x
+
+    def mlp_forward(self, x, stream=None):
+        import torch
+        z = torch.empty((x.shape[0], MLP_OUT), dtype=torch.float32, device=x.device)
+        self.check(load().p2s_mlp_forward(self._h, x.shape[0], _dev_ptr(x), _dev_ptr(z), _stream(stream)),
+                   "p2s_mlp_forward")
+        return z
+
+    def mlp_gradients(self, x, labels, stream=None):
+        """(loss sum, gradient of the mean loss) for a batch."""
+        import torch
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        self.check(load().p2s_mlp_gradients(self._h, x.shape[0], _dev_ptr(x), _dev_ptr(labels), _dev_ptr(g),
+                                            _dev_ptr(loss), _stream(stream)), "p2s_mlp_gradients")
+        return loss, g
+
+    def mlp_train_step(self, x, labels, lr, loss, stream=None):
+        self.check(load().p2s_mlp_train_step(self._h, x.shape[0], _dev_ptr(x), _dev_ptr(labels), float(lr),
+                                             _dev_ptr(loss), _stream(stream)), "p2s_mlp_train_step")
+
+    def mlp_predict(self, x, p_cover=0.99, stream=None):
+        import torch
+        q = torch.empty((x.shape[0], 3), dtype=torch.int32, device=x.device)
+        self.check(load().p2s_mlp_predict(self._h, x.shape[0], _dev_ptr(x), float(p_cover), _dev_ptr(q),
+                                          _stream(stream)), "p2s_mlp_predict")
+        return q
+
+    def rel_error(self, a, b, offsets=None, block=0, stream=None):
+        """Per-element ||a-b||/||b|| of device blocks (offsets: device int64 [E+1])."""
+        import torch
+        E = (offsets.numel() - 1) if offsets is not None else a.numel() // block
+        err = torch.empty(E, dtype=torch.float64, device=a.device)
+        self.check(load().p2s_rel_error(self._h, E, block, _dev_ptr(offsets), _dev_ptr(a), _dev_ptr(b),
+                                        _dev_ptr(err), _stream(stream)), "p2s_rel_error")
+        return err
+
     def plan(self, problem, material, orders, quad, precision=FP64, method=METHOD_P2S,
              stiff_scale=1.0, mass_scale=1.0) -> "Plan":
         return Plan(self, terms(problem, material, precision, method, stiff_scale, mass_scale), orders, quad)
@@ -251,6 +336,20 @@ class Plan:
 
     def replay(self, stream=None):
         self.ctx.check(load().p2s_plan_replay(self._h, _stream(stream)), "p2s_plan_replay")
+
+    def set_learned(self, enable=True, p_cover=0.99, theta=1e-9):
+        self.ctx.check(load().p2s_plan_set_learned(self._h, int(enable), float(p_cover), float(theta)),
+                       "p2s_plan_set_learned")
+
+    def tail_values(self) -> np.ndarray:
+        t = np.zeros(self.E)
+        self.ctx.check(load().p2s_plan_tail_values(self._h, _np_ptr(t)), "p2s_plan_tail_values")
+        return t
+
+    def rules(self) -> np.ndarray:
+        q = np.zeros((self.E, 3), np.int32)
+        self.ctx.check(load().p2s_plan_rules(self._h, _np_ptr(q)), "p2s_plan_rules")
+        return q
 
     def coupling(self, nodes, material, stream=None):
         import torch

@@ -7,6 +7,7 @@
 #include <array>
 #include <cstdarg>
 #include <cstdlib>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -26,6 +27,13 @@ struct p2s_ctx_s {
     int device = 0;
     double *d_tab = nullptr;
     std::string err;
+    // learned quadrature order: network parameters, Adam state, training scratch
+    bool mlp_ready = false;
+    float *d_mlp = nullptr, *d_grad = nullptr, *d_adam_m = nullptr, *d_adam_v = nullptr;
+    int adam_step = 0;
+    int64_t mlp_bmax = 0;
+    float *d_h1 = nullptr, *d_h2 = nullptr, *d_z = nullptr, *d_dz = nullptr, *d_dh2 = nullptr, *d_dh1 = nullptr,
+          *d_lossb = nullptr;
 };
 
 struct Chunk {
@@ -60,6 +68,14 @@ struct p2s_plan_s {
     WorkItem *d_items = nullptr;
     int32_t *d_counter = nullptr;
     int num_cu = 256;
+    // learned quadrature order
+    bool learned = false;
+    float p_cover = 0.99f;
+    double theta = 1e-9;
+    float *d_lx = nullptr, *d_lh1 = nullptr, *d_lh2 = nullptr, *d_lz = nullptr;
+    int32_t *d_redo = nullptr;
+    double *d_tau = nullptr;  // tail statistic of the last learned execution
+    std::vector<ElemDesc> desc_host;
     // captured execution
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -192,6 +208,9 @@ void p2s_destroy(p2s_ctx ctx)
     if (!ctx) return;
     hipSetDevice(ctx->device);
     if (ctx->d_tab) hipFree(ctx->d_tab);
+    for (float *p : {ctx->d_mlp, ctx->d_grad, ctx->d_adam_m, ctx->d_adam_v, ctx->d_h1, ctx->d_h2, ctx->d_z,
+                     ctx->d_dz, ctx->d_dh2, ctx->d_dh1, ctx->d_lossb})
+        if (p) hipFree(p);
     delete ctx;
 }
 
@@ -206,6 +225,12 @@ void p2s_plan_destroy(p2s_plan plan)
     hipFree(plan->d_stage_status);
     hipFree(plan->d_items);
     hipFree(plan->d_counter);
+    hipFree(plan->d_lx);
+    hipFree(plan->d_lh1);
+    hipFree(plan->d_lh2);
+    hipFree(plan->d_lz);
+    hipFree(plan->d_redo);
+    hipFree(plan->d_tau);
     if (plan->gexec) hipGraphExecDestroy(plan->gexec);
     if (plan->graph) hipGraphDestroy(plan->graph);
     for (auto &v : plan->ev)
@@ -390,6 +415,7 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
         plan->mode = 1;
         plan->wpc = 1;
     }
+    plan->desc_host = desc;
     if (E > 0) {
         if (hipMemcpy(plan->d_desc, desc.data(), sizeof(ElemDesc) * E, hipMemcpyHostToDevice) != hipSuccess ||
             (!elist.empty() && hipMemcpy(plan->d_elist, elist.data(), sizeof(int32_t) * elist.size(),
@@ -417,10 +443,20 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     const int problem = plan->terms.problem;
     const int F = num_fields(problem);
+    const bool learned = plan->learned && stop == STOP_FULL;
+    if (learned) {
+        if (!ctx->mlp_ready) return fail(ctx, P2S_ENOMODEL, "execute: learned order needs a loaded network");
+        // features -> network -> per-axis rule, written into the descriptors
+        prof_begin(plan, 3, st);
+        launch_features(plan->E, nodes, material, plan->terms.material, plan->mat_stride, plan->d_lx, st);
+        launch_mlp_forward(plan->E, ctx->d_mlp, plan->d_lx, plan->d_lh1, plan->d_lh2, plan->d_lz, st);
+        launch_choose(plan->E, plan->d_lz, plan->p_cover, nullptr, plan->d_desc, st);
+        prof_end(plan, 3, st);
+    }
     for (const Chunk &c : plan->chunks) {
         prof_begin(plan, 0, st);
         launch_coupling(problem, plan->d_desc, c.e0, c.count, nodes, material, plan->terms.material,
-                        plan->mat_stride, ctx->d_tab, plan->d_alpha, status, st);
+                        plan->mat_stride, ctx->d_tab, plan->d_alpha, status, nullptr, st);
         prof_end(plan, 0, st);
         if (plan->terms.method == P2S_METHOD_DIRECT && stop == STOP_FULL) {
             prof_begin(plan, 3, st);
@@ -437,8 +473,21 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         }
         prof_begin(plan, 1, st);
         launch_moments(problem, plan->maxN, plan->maxQu, plan->maxQuv, plan->d_desc, c.e0, c.count,
-                       plan->d_alpha, ctx->d_tab, plan->d_mom, st);
+                       plan->d_alpha, ctx->d_tab, plan->d_mom, nullptr, st);
         prof_end(plan, 1, st);
+        if (learned) {
+            // tail check; rejected elements are sampled again with the full rule
+            prof_begin(plan, 3, st);
+            launch_tail(plan->d_desc, c.e0, c.count, F, plan->d_alpha, ctx->d_tab, plan->theta, MLP_KMAX, 0,
+                        plan->d_redo, status, plan->d_tau, st);
+            launch_coupling(problem, plan->d_desc, c.e0, c.count, nodes, material, plan->terms.material,
+                            plan->mat_stride, ctx->d_tab, plan->d_alpha, status, plan->d_redo, st);
+            launch_moments(problem, plan->maxN, plan->maxQu, plan->maxQuv, plan->d_desc, c.e0, c.count,
+                           plan->d_alpha, ctx->d_tab, plan->d_mom, plan->d_redo, st);
+            launch_tail(plan->d_desc, c.e0, c.count, F, plan->d_alpha, ctx->d_tab, plan->theta, MLP_KMAX, 1,
+                        plan->d_redo, status, nullptr, st);
+            prof_end(plan, 3, st);
+        }
         if (stop == STOP_MOMENTS) {
             const int K = 2 * plan->N - 1;
             const int64_t per = (int64_t)F * K * K * K;
@@ -704,6 +753,252 @@ int p2s_plan_replay(p2s_plan plan, void *stream)
     if (!plan) return P2S_EINVAL;
     if (!plan->gexec) return fail(plan->ctx, P2S_EINVAL, "replay: no captured execution");
     HIP_TRY(plan->ctx, hipGraphLaunch(plan->gexec, (hipStream_t)stream));
+    return P2S_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned quadrature order
+
+static int mlp_alloc(p2s_ctx ctx, int64_t bmax)
+{
+    if (!ctx->d_mlp) {
+        for (float **p : {&ctx->d_mlp, &ctx->d_grad, &ctx->d_adam_m, &ctx->d_adam_v})
+            if (hipMalloc(p, sizeof(float) * MLP_PARAMS) != hipSuccess)
+                return fail(ctx, P2S_ENOMEM, "network: allocation failed");
+        hipMemset(ctx->d_adam_m, 0, sizeof(float) * MLP_PARAMS);
+        hipMemset(ctx->d_adam_v, 0, sizeof(float) * MLP_PARAMS);
+    }
+    if (bmax > ctx->mlp_bmax) {
+        for (float *p : {ctx->d_h1, ctx->d_h2, ctx->d_z, ctx->d_dz, ctx->d_dh2, ctx->d_dh1, ctx->d_lossb})
+            if (p) hipFree(p);
+        bool ok = hipMalloc(&ctx->d_h1, sizeof(float) * bmax * MLP_H) == hipSuccess &&
+                  hipMalloc(&ctx->d_h2, sizeof(float) * bmax * MLP_H) == hipSuccess &&
+                  hipMalloc(&ctx->d_z, sizeof(float) * bmax * MLP_OUT) == hipSuccess &&
+                  hipMalloc(&ctx->d_dz, sizeof(float) * bmax * MLP_OUT) == hipSuccess &&
+                  hipMalloc(&ctx->d_dh2, sizeof(float) * bmax * MLP_H) == hipSuccess &&
+                  hipMalloc(&ctx->d_dh1, sizeof(float) * bmax * MLP_H) == hipSuccess &&
+                  hipMalloc(&ctx->d_lossb, sizeof(float) * bmax) == hipSuccess;
+        if (!ok) return fail(ctx, P2S_ENOMEM, "network: scratch allocation failed");
+        ctx->mlp_bmax = bmax;
+    }
+    return P2S_OK;
+}
+
+int p2s_mlp_init(p2s_ctx ctx, uint64_t seed, int64_t max_batch)
+{
+    if (!ctx) return P2S_EINVAL;
+    if (max_batch < 1) return fail(ctx, P2S_EINVAL, "network: max_batch must be positive");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    int r = mlp_alloc(ctx, max_batch);
+    if (r != P2S_OK) return r;
+    // He-normal weights from a splitmix64 stream (Box-Muller), zero biases
+    std::vector<float> p(MLP_PARAMS, 0.f);
+    uint64_t x = seed;
+    auto next = [&]() {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return (double)((z ^ (z >> 31)) >> 11) * (1.0 / 9007199254740992.0);
+    };
+    auto fill = [&](int off, int fan_in, int n) {
+        const double sd = std::sqrt(2.0 / fan_in);
+        for (int i = 0; i < n; ++i) {
+            const double u1 = next() + 1e-300, u2 = next();
+            p[off + i] = (float)(sd * std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2));
+        }
+    };
+    fill(MLP_OFF_W1, MLP_IN, MLP_IN * MLP_H);
+    fill(MLP_OFF_W2, MLP_H, MLP_H * MLP_H);
+    fill(MLP_OFF_W3, MLP_H, MLP_H * MLP_OUT);
+    HIP_TRY(ctx, hipMemcpy(ctx->d_mlp, p.data(), sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemset(ctx->d_adam_m, 0, sizeof(float) * MLP_PARAMS));
+    HIP_TRY(ctx, hipMemset(ctx->d_adam_v, 0, sizeof(float) * MLP_PARAMS));
+    ctx->adam_step = 0;
+    ctx->mlp_ready = true;
+    return P2S_OK;
+}
+
+int p2s_mlp_set_params(p2s_ctx ctx, const float *params)
+{
+    if (!ctx || !params) return P2S_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    int r = mlp_alloc(ctx, std::max<int64_t>(ctx->mlp_bmax, 1));
+    if (r != P2S_OK) return r;
+    HIP_TRY(ctx, hipMemcpy(ctx->d_mlp, params, sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice));
+    ctx->mlp_ready = true;
+    return P2S_OK;
+}
+
+int p2s_mlp_get_params(p2s_ctx ctx, float *params)
+{
+    if (!ctx || !params) return P2S_EINVAL;
+    if (!ctx->mlp_ready) return fail(ctx, P2S_ENOMODEL, "network: no parameters");
+    HIP_TRY(ctx, hipMemcpy(params, ctx->d_mlp, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToHost));
+    return P2S_OK;
+}
+
+// File: "P2SK" magic, int32 version 1, int32 (in, hidden, out), float32 params.
+int p2s_mlp_save(p2s_ctx ctx, const char *path)
+{
+    if (!ctx || !path) return P2S_EINVAL;
+    std::vector<float> p(MLP_PARAMS);
+    int r = p2s_mlp_get_params(ctx, p.data());
+    if (r != P2S_OK) return r;
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(ctx, P2S_EINVAL, "network: cannot write %s", path);
+    const int32_t hdr[4] = {1, MLP_IN, MLP_H, MLP_OUT};
+    bool ok = fwrite("P2SK", 1, 4, f) == 4 && fwrite(hdr, sizeof(hdr), 1, f) == 1 &&
+              fwrite(p.data(), sizeof(float), MLP_PARAMS, f) == (size_t)MLP_PARAMS;
+    fclose(f);
+    return ok ? P2S_OK : fail(ctx, P2S_EINVAL, "network: short write to %s", path);
+}
+
+int p2s_mlp_load(p2s_ctx ctx, const char *path)
+{
+    if (!ctx || !path) return P2S_EINVAL;
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(ctx, P2S_EINVAL, "network: cannot read %s", path);
+    char magic[4];
+    int32_t hdr[4];
+    std::vector<float> p(MLP_PARAMS);
+    bool ok = fread(magic, 1, 4, f) == 4 && std::memcmp(magic, "P2SK", 4) == 0 && fread(hdr, sizeof(hdr), 1, f) == 1 &&
+              hdr[0] == 1 && hdr[1] == MLP_IN && hdr[2] == MLP_H && hdr[3] == MLP_OUT &&
+              fread(p.data(), sizeof(float), MLP_PARAMS, f) == (size_t)MLP_PARAMS;
+    fclose(f);
+    if (!ok) return fail(ctx, P2S_EINVAL, "network: %s is not a network file of this shape", path);
+    return p2s_mlp_set_params(ctx, p.data());
+}
+
+int p2s_features(p2s_ctx ctx, int material, int64_t E, const double *nodes, const double *mat, float *x,
+                 void *stream)
+{
+    if (!ctx || E < 0 || (E > 0 && (!nodes || !mat || !x))) return P2S_EINVAL;
+    int stride = material == P2S_MAT_SINCOSEXP ? 1 : material == P2S_MAT_ROTDIAG ? 12
+               : material == P2S_MAT_PLANEWAVE ? 4 : -1;
+    if (stride < 0) return fail(ctx, P2S_EINVAL, "features: bad material %d", material);
+    launch_features(E, nodes, mat, material, stride, x, (hipStream_t)stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return P2S_OK;
+}
+
+static int mlp_check_batch(p2s_ctx ctx, int64_t B)
+{
+    if (!ctx->mlp_ready) return fail(ctx, P2S_ENOMODEL, "network: not initialised or loaded");
+    if (B < 1 || B > ctx->mlp_bmax) return fail(ctx, P2S_EINVAL, "network: batch %lld outside 1..%lld",
+                                                (long long)B, (long long)ctx->mlp_bmax);
+    return P2S_OK;
+}
+
+int p2s_mlp_forward(p2s_ctx ctx, int64_t B, const float *x, float *logits, void *stream)
+{
+    if (!ctx || !x || !logits) return P2S_EINVAL;
+    int r = mlp_check_batch(ctx, B);
+    if (r != P2S_OK) return r;
+    launch_mlp_forward(B, ctx->d_mlp, x, ctx->d_h1, ctx->d_h2, logits, (hipStream_t)stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return P2S_OK;
+}
+
+int p2s_mlp_gradients(p2s_ctx ctx, int64_t B, const float *x, const int32_t *labels, float *grad, float *loss,
+                      void *stream)
+{
+    if (!ctx || !x || !labels || !loss) return P2S_EINVAL;
+    int r = mlp_check_batch(ctx, B);
+    if (r != P2S_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    launch_mlp_forward(B, ctx->d_mlp, x, ctx->d_h1, ctx->d_h2, ctx->d_z, st);
+    launch_mlp_backward(B, ctx->d_mlp, x, ctx->d_h1, ctx->d_h2, ctx->d_z, labels, ctx->d_dz, ctx->d_dh2,
+                        ctx->d_dh1, ctx->d_grad, ctx->d_lossb, loss, st);
+    if (grad)
+        HIP_TRY(ctx, hipMemcpyAsync(grad, ctx->d_grad, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(ctx, hipGetLastError());
+    return P2S_OK;
+}
+
+int p2s_mlp_train_step(p2s_ctx ctx, int64_t B, const float *x, const int32_t *labels, float lr, float *loss,
+                       void *stream)
+{
+    int r = p2s_mlp_gradients(ctx, B, x, labels, nullptr, loss, stream);
+    if (r != P2S_OK) return r;
+    launch_adam(ctx->d_mlp, ctx->d_grad, ctx->d_adam_m, ctx->d_adam_v, lr, ++ctx->adam_step, (hipStream_t)stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return P2S_OK;
+}
+
+int p2s_mlp_predict(p2s_ctx ctx, int64_t B, const float *x, float p_cover, int32_t *quad, void *stream)
+{
+    if (!ctx || !x || !quad) return P2S_EINVAL;
+    int r = mlp_check_batch(ctx, B);
+    if (r != P2S_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    launch_mlp_forward(B, ctx->d_mlp, x, ctx->d_h1, ctx->d_h2, ctx->d_z, st);
+    launch_choose(B, ctx->d_z, p_cover, quad, nullptr, st);
+    HIP_TRY(ctx, hipGetLastError());
+    return P2S_OK;
+}
+
+int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, double theta)
+{
+    if (!plan) return P2S_EINVAL;
+    p2s_ctx ctx = plan->ctx;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (!enable) {
+        plan->learned = false;
+        if (plan->E > 0)
+            HIP_TRY(ctx, hipMemcpy(plan->d_desc, plan->desc_host.data(), sizeof(ElemDesc) * plan->E,
+                                   hipMemcpyHostToDevice));
+        return P2S_OK;
+    }
+    if (plan->terms.material == P2S_ALPHA_SAMPLED || plan->terms.method != P2S_METHOD_P2S || !plan->uniform ||
+        plan->Qu != MLP_KMAX || plan->Qv != MLP_KMAX || plan->Qw != MLP_KMAX)
+        return fail(ctx, P2S_EINVAL, "learned order: needs a uniform product-to-sum plan created with %d points "
+                                     "per axis", MLP_KMAX);
+    if (!(p_cover > 0.f && p_cover <= 1.f) || !(theta > 0.0)) return fail(ctx, P2S_EINVAL, "learned order: bad p/theta");
+    if (!plan->d_lx && plan->E > 0) {
+        const int64_t E = plan->E;
+        bool ok = hipMalloc(&plan->d_lx, sizeof(float) * E * MLP_IN) == hipSuccess &&
+                  hipMalloc(&plan->d_lh1, sizeof(float) * E * MLP_H) == hipSuccess &&
+                  hipMalloc(&plan->d_lh2, sizeof(float) * E * MLP_H) == hipSuccess &&
+                  hipMalloc(&plan->d_lz, sizeof(float) * E * MLP_OUT) == hipSuccess &&
+                  hipMalloc(&plan->d_redo, sizeof(int32_t) * E) == hipSuccess &&
+                  hipMalloc(&plan->d_tau, sizeof(double) * E) == hipSuccess;
+        if (!ok) return fail(ctx, P2S_ENOMEM, "learned order: workspace allocation failed");
+        plan->bytes += E * (int64_t)(4 * (MLP_IN + 2 * MLP_H + MLP_OUT) + 12);
+    }
+    plan->learned = true;
+    plan->p_cover = p_cover;
+    plan->theta = theta;
+    return P2S_OK;
+}
+
+int p2s_plan_rules(p2s_plan plan, int32_t *quad)
+{
+    if (!plan || (!quad && plan->E > 0)) return P2S_EINVAL;
+    std::vector<ElemDesc> d(plan->E);
+    if (plan->E > 0)
+        HIP_TRY(plan->ctx, hipMemcpy(d.data(), plan->d_desc, sizeof(ElemDesc) * plan->E, hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < plan->E; ++e) {
+        quad[3 * e] = d[e].Qu;
+        quad[3 * e + 1] = d[e].Qv;
+        quad[3 * e + 2] = d[e].Qw;
+    }
+    return P2S_OK;
+}
+
+int p2s_plan_tail_values(p2s_plan plan, double *tau)
+{
+    if (!plan || (!tau && plan->E > 0)) return P2S_EINVAL;
+    if (!plan->d_tau) return fail(plan->ctx, P2S_EINVAL, "tail values: the plan has not run in learned mode");
+    HIP_TRY(plan->ctx, hipMemcpy(tau, plan->d_tau, sizeof(double) * plan->E, hipMemcpyDeviceToHost));
+    return P2S_OK;
+}
+
+int p2s_rel_error(p2s_ctx ctx, int64_t E, int64_t len, const int64_t *offsets, const double *a, const double *b,
+                  double *err, void *stream)
+{
+    if (!ctx || E < 0 || (E > 0 && (!a || !b || !err)) || (!offsets && len < 1)) return P2S_EINVAL;
+    launch_rel_error(E, len, offsets, a, b, err, (hipStream_t)stream);
+    HIP_TRY(ctx, hipGetLastError());
     return P2S_OK;
 }
 

@@ -111,6 +111,18 @@ constexpr uint32_t P2S_STATUS_NONFINITE_BIT = 2u;
 constexpr uint32_t P2S_STATUS_FALLBACK_BIT = 4u;
 constexpr uint32_t P2S_STATUS_TAIL_BIT = 8u;
 
+// Learned quadrature order: network shape and parameter layout (FP32).
+// Weights are stored input-major, W[i][o]: y_o = sum_i x_i W[i][o] + b_o.
+constexpr int MLP_IN = 85, MLP_H = 128, MLP_NCLS = 19, MLP_OUT = 3 * MLP_NCLS;
+constexpr int MLP_KMIN = 6, MLP_KMAX = MLP_KMIN + MLP_NCLS - 1;  // K in {6..24}
+constexpr int MLP_OFF_W1 = 0;
+constexpr int MLP_OFF_B1 = MLP_OFF_W1 + MLP_IN * MLP_H;
+constexpr int MLP_OFF_W2 = MLP_OFF_B1 + MLP_H;
+constexpr int MLP_OFF_B2 = MLP_OFF_W2 + MLP_H * MLP_H;
+constexpr int MLP_OFF_W3 = MLP_OFF_B2 + MLP_H;
+constexpr int MLP_OFF_B3 = MLP_OFF_W3 + MLP_H * MLP_OUT;
+constexpr int MLP_PARAMS = MLP_OFF_B3 + MLP_OUT;
+
 // Work item of the persistent contraction: rows (m1, ., .) of component
 // `comp` of element e.
 struct WorkItem {

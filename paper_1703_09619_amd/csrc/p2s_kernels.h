@@ -13,11 +13,14 @@ constexpr size_t LDS_LIMIT = 160 * 1024;
 int prepare_kernels();
 size_t moments_smem_bytes(int maxN, int maxQu, int maxQuv);
 
+// `only` (may be null): elements with only[e] == 0 are skipped; with it the
+// coupling kernel ORs its status bits instead of overwriting them.
 void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t count,
                      const double *nodes, const double *mat, int kind, int mat_stride,
-                     const double *tab, double *alpha, uint32_t *status, hipStream_t st);
+                     const double *tab, double *alpha, uint32_t *status, const int32_t *only, hipStream_t st);
 void launch_moments(int problem, int maxN, int maxQu, int maxQuv, const ElemDesc *desc, int64_t e0,
-                    int64_t count, const double *alpha, const double *tab, double *mom, hipStream_t st);
+                    int64_t count, const double *alpha, const double *tab, double *mom, const int32_t *only,
+                    hipStream_t st);
 int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0,
                     int64_t count, const double *tab, const double *mom, double *out, uint32_t *status,
                     double sK, double sM, hipStream_t st);
@@ -30,5 +33,20 @@ int launch_contract_persistent(int problem, const ElemDesc *desc, const WorkItem
 // Direct quadrature of eq. (2) (baseline method), from coupling samples.
 void launch_direct(int problem, int N, const ElemDesc *desc, int64_t e0, int64_t count, const double *tab,
                    const double *alpha, double *out, double sK, double sM, hipStream_t st);
+
+// Learned quadrature order (p2s_learned.hip)
+void launch_features(int64_t E, const double *nodes, const double *mat, int kind, int stride, float *X,
+                     hipStream_t st);
+void launch_mlp_forward(int64_t B, const float *params, const float *X, float *H1, float *H2, float *Z,
+                        hipStream_t st);
+void launch_mlp_backward(int64_t B, const float *params, const float *X, const float *H1, const float *H2,
+                         const float *Z, const int32_t *labels, float *dZ, float *dH2, float *dH1, float *grad,
+                         float *loss_b, float *loss, hipStream_t st);
+void launch_adam(float *params, const float *grad, float *m, float *v, float lr, int step, hipStream_t st);
+void launch_choose(int64_t E, const float *Z, float p_cover, int32_t *quad, ElemDesc *desc, hipStream_t st);
+void launch_tail(ElemDesc *desc, int64_t e0, int64_t count, int F, const double *alpha, const double *tab,
+                 double theta, int qfull, int mode, int32_t *redo, uint32_t *status, double *tau, hipStream_t st);
+void launch_rel_error(int64_t E, int64_t len, const int64_t *off, const double *a, const double *b, double *err,
+                      hipStream_t st);
 
 }  // namespace p2s

@@ -145,10 +145,12 @@ __global__ __launch_bounds__(256) void k_coupling(const ElemDesc *__restrict__ d
                                                   const double *__restrict__ mat, int kind,
                                                   int mat_stride, const double *__restrict__ tab,
                                                   double *__restrict__ alpha,
-                                                  uint32_t *__restrict__ status)
+                                                  uint32_t *__restrict__ status,
+                                                  const int32_t *__restrict__ only)
 {
     constexpr int F = num_fields(PROB);
     const int64_t e = e0 + blockIdx.x;
+    if (only && !only[e]) return;
     const ElemDesc d = desc[e];
     const int Qu = d.Qu, Qv = d.Qv, Qw = d.Qw;
     const int P = Qu * Qv * Qw;
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(256) void k_coupling(const ElemDesc *__restrict__ d
     if (kind == ALPHA_SAMPLED) {
         const double *src = mat + e * (int64_t)(F * P);
         for (int i = threadIdx.x; i < F * P; i += blockDim.x) dst[i] = src[i];
-        if (threadIdx.x == 0) status[e] = 0u;
+        if (threadIdx.x == 0 && !only) status[e] = 0u;
         return;
     }
     if (threadIdx.x < 81) X[threadIdx.x] = nodes[e * 81 + threadIdx.x];
@@ -179,7 +181,12 @@ __global__ __launch_bounds__(256) void k_coupling(const ElemDesc *__restrict__ d
         for (int s = 0; s < F; ++s) dst[(int64_t)s * P + pt] = f[s];
     }
     bad = __syncthreads_or(bad);
-    if (threadIdx.x == 0) status[e] = bad ? P2S_STATUS_DETJ_BIT : 0u;
+    if (threadIdx.x == 0) {
+        if (only)
+            status[e] |= bad ? P2S_STATUS_DETJ_BIT : 0u;
+        else
+            status[e] = bad ? P2S_STATUS_DETJ_BIT : 0u;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -253,9 +260,11 @@ __device__ void moments_body(const ElemDesc &d, int f, int F, const double *__re
 __global__ __launch_bounds__(256) void k_moments(const ElemDesc *__restrict__ desc, int64_t e0, int F,
                                                  const double *__restrict__ alpha,
                                                  const double *__restrict__ tab,
-                                                 double *__restrict__ mom, int p2off)
+                                                 double *__restrict__ mom, int p2off,
+                                                 const int32_t *__restrict__ only)
 {
     extern __shared__ double sm[];
+    if (only && !only[e0 + blockIdx.x]) return;
     const ElemDesc d = desc[e0 + blockIdx.x];
     const int f = blockIdx.y;
     switch (d.N) {
@@ -284,25 +293,26 @@ size_t moments_smem_bytes(int maxN, int maxQu, int maxQuv)
 
 void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t count,
                      const double *nodes, const double *mat, int kind, int mat_stride,
-                     const double *tab, double *alpha, uint32_t *status, hipStream_t st)
+                     const double *tab, double *alpha, uint32_t *status, const int32_t *only, hipStream_t st)
 {
     if (count <= 0) return;
     if (problem == 0)
         hipLaunchKernelGGL(k_coupling<0>, dim3((unsigned)count), dim3(256), 0, st, desc, e0, nodes,
-                           mat, kind, mat_stride, tab, alpha, status);
+                           mat, kind, mat_stride, tab, alpha, status, only);
     else
         hipLaunchKernelGGL(k_coupling<1>, dim3((unsigned)count), dim3(256), 0, st, desc, e0, nodes,
-                           mat, kind, mat_stride, tab, alpha, status);
+                           mat, kind, mat_stride, tab, alpha, status, only);
 }
 
 void launch_moments(int problem, int maxN, int maxQu, int maxQuv, const ElemDesc *desc, int64_t e0,
-                    int64_t count, const double *alpha, const double *tab, double *mom, hipStream_t st)
+                    int64_t count, const double *alpha, const double *tab, double *mom, const int32_t *only,
+                    hipStream_t st)
 {
     if (count <= 0) return;
     const int F = num_fields(problem);
     hipLaunchKernelGGL(k_moments, dim3((unsigned)count, F), dim3(256),
                        moments_smem_bytes(maxN, maxQu, maxQuv), st, desc, e0, F, alpha, tab, mom,
-                       moments_p2_offset(maxN, maxQuv));
+                       moments_p2_offset(maxN, maxQuv), only);
 }
 
 int prepare_kernels()

@@ -1,0 +1,186 @@
+"""GPU tests of the learned quadrature order: the network kernels against
+the FP64 CPU reference (oracle/mlp.py), the order choice, training, and the
+learned fill (fallback and accuracy judged by the full-rule fill)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    from oracle import mlp
+    import paper_1703_09619_amd as p2s
+    from paper_1703_09619_amd import workloads as W
+    oracle.build(force=False)
+    ctx = p2s.Context(0)
+    ctx.mlp_init(seed=7, max_batch=512)
+    return dict(torch=torch, oracle=oracle, mlp=mlp, p2s=p2s, W=W, ctx=ctx)
+
+
+def rand_params(mlp, seed):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(mlp.NPARAMS)
+    o = 0
+    for name, shape in mlp.SHAPES:
+        n = int(np.prod(shape))
+        fan_in = shape[0] if len(shape) == 2 else 1
+        p[o:o + n] = rng.standard_normal(n) * (math.sqrt(2.0 / fan_in) if len(shape) == 2 else 0.1)
+        o += n
+    return p.astype(np.float32)
+
+
+def test_features(env):
+    torch, W, ctx = env["torch"], env["W"], env["ctx"]
+    w = W.make("scalar_planewave", E=33)
+    x = ctx.features(w.material, torch.from_numpy(w.nodes).cuda(), torch.from_numpy(w.mat).cuda()).cpu().numpy()
+    ref = np.zeros((w.E, 85), np.float32)
+    nom = W.nominal_nodes().reshape(-1)
+    ref[:, :81] = ((w.nodes.reshape(w.E, -1) - nom) / 0.3).astype(np.float32)
+    ref[:, 81:84] = (np.abs(w.mat[:, :3]) / (16 * np.pi)).astype(np.float32)
+    ref[:, 84] = (w.mat[:, 3] / (2 * np.pi) - 0.5).astype(np.float32)
+    assert np.abs(x - ref).max() <= 1e-6
+
+
+def test_forward_and_gradients_match_fp64_reference(env):
+    torch, mlp, ctx = env["torch"], env["mlp"], env["ctx"]
+    p = rand_params(mlp, 1)
+    ctx.mlp_set_params(p)
+    rng = np.random.default_rng(2)
+    B = 200
+    x = rng.standard_normal((B, 85)).astype(np.float32)
+    y = rng.integers(0, 19, size=(B, 3)).astype(np.int32)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    z = ctx.mlp_forward(xd).cpu().numpy()
+    zr, _, _ = mlp.forward(p.astype(np.float64), x.astype(np.float64))
+    assert np.abs(z - zr).max() <= 2e-5 * max(1.0, np.abs(zr).max())
+    loss, g = ctx.mlp_gradients(xd, yd)
+    lr, gr = mlp.loss_and_grad(p.astype(np.float64), x.astype(np.float64), y)
+    assert abs(float(loss.item()) - lr) <= 1e-5 * lr
+    g = g.cpu().numpy()
+    assert np.abs(g - gr).max() <= 1e-5 * max(1e-3, np.abs(gr).max())
+    # every layer's weight and bias blocks agree in norm
+    o = 0
+    for name, shape in mlp.SHAPES:
+        n = int(np.prod(shape))
+        a, b = g[o:o + n], gr[o:o + n]
+        assert np.linalg.norm(a - b) <= 1e-4 * max(np.linalg.norm(b), 1e-8), name
+        o += n
+
+
+def test_adam_step_matches_reference(env):
+    torch, mlp, ctx = env["torch"], env["mlp"], env["ctx"]
+    ctx.mlp_init(seed=3, max_batch=512)
+    p0 = ctx.mlp_params().astype(np.float64)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((64, 85)).astype(np.float32)
+    y = rng.integers(0, 19, size=(64, 3)).astype(np.int32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ctx.mlp_train_step(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), 1e-3, loss)
+    p1 = ctx.mlp_params().astype(np.float64)
+    _, g = mlp.loss_and_grad(p0, x.astype(np.float64), y)
+    pr, _, _ = mlp.adam(p0, g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
+    # first Adam step moves every parameter by ~lr*sign(g) (unless g ~ 0)
+    big = np.abs(g) > 1e-4
+    assert np.abs(p1 - pr)[big].max() <= 1e-6
+
+
+def test_predict_matches_reference_choice(env):
+    torch, mlp, ctx = env["torch"], env["mlp"], env["ctx"]
+    p = rand_params(mlp, 5)
+    ctx.mlp_set_params(p)
+    x = np.random.default_rng(6).standard_normal((300, 85)).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    q = ctx.mlp_predict(xd, 0.9).cpu().numpy()
+    z = ctx.mlp_forward(xd).cpu().numpy()
+    qr = mlp.choose(z, 0.9)
+    assert (q == qr).mean() > 0.995  # ties at the threshold may round either way
+    assert q.min() >= 6 and q.max() <= 24
+
+
+def test_training_reduces_loss(env):
+    torch, ctx = env["torch"], env["ctx"]
+    from paper_1703_09619_amd import learned_k
+    ctx.mlp_init(seed=11, max_batch=512)
+    rng = np.random.default_rng(12)
+    n = 4096
+    x = rng.standard_normal((n, 85)).astype(np.float32)
+    # a learnable rule: class from the sign pattern of three features
+    y = np.stack([(x[:, 81] > 0) * 10 + 2, (x[:, 82] > 0) * 8 + 1, (x[:, 83] > 0) * 5], 1).astype(np.int32)
+    hist = learned_k.train(ctx, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), epochs=8, batch=256,
+                           lr=3e-3, log=lambda m: None)
+    assert hist[-1] < 0.2 * hist[0]
+
+
+def test_learned_fill_forced_fallback_equals_full_rule(env):
+    """theta tiny: every element is sent back to the full rule, and the
+    result equals the plain full-rule fill bit for bit."""
+    torch, W, ctx, p2s = env["torch"], env["W"], env["ctx"], env["p2s"]
+    ctx.mlp_init(seed=13, max_batch=512)
+    w = W.make("scalar_planewave", E=96)
+    nodes, mat = torch.from_numpy(w.nodes).cuda(), torch.from_numpy(w.mat).cuda()
+    full = np.full((w.E, 3), 24, np.int32)
+    pf = ctx.plan(w.problem, w.material, w.orders, full)
+    ref, rst = pf.execute(nodes, mat)
+    pl = ctx.plan(w.problem, w.material, w.orders, full)
+    pl.set_learned(True, 0.99, 1e-300)
+    out, st = pl.execute(nodes, mat)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    stn = st.cpu().numpy()
+    assert ((stn & p2s.STATUS_FALLBACK) != 0).all()
+    assert (pl.rules() == 24).all()
+    # switching learned mode off restores the plan's own rules
+    pl.set_learned(False)
+    out2, _ = pl.execute(nodes, mat)
+    torch.cuda.synchronize()
+    assert torch.equal(out2, ref)
+
+
+def test_learned_fill_requires_model_and_full_rule(env):
+    p2s = env["p2s"]
+    ctx2 = p2s.Context(0)
+    pl = ctx2.plan(0, 2, [6], [[24, 24, 24]])
+    pl.set_learned(True, 0.99, 1e-9)
+    import torch
+    with pytest.raises(p2s.P2SError, match="network"):
+        pl.execute(torch.zeros((1, 27, 3), dtype=torch.float64, device="cuda"),
+                   torch.zeros((1, 4), dtype=torch.float64, device="cuda"))
+    with pytest.raises(p2s.P2SError, match="24 points"):
+        ctx2.plan(0, 2, [6], [[12, 24, 24]]).set_learned(True, 0.99, 1e-9)
+
+
+MODEL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1703_09619_amd", "models",
+                     "kmodel_scalar_n6.p2sk")
+
+
+@pytest.mark.skipif(not os.path.exists(MODEL), reason="no trained model in the tree")
+def test_trained_model_accuracy_and_gain(env):
+    """With the committed trained network: on held-out elements the learned
+    fill stays within 1e-8 of the full-rule fill and is faster; two elements
+    at their chosen rules agree with the oracle to rounding."""
+    import json
+    torch, W, ctx, oracle = env["torch"], env["W"], env["ctx"], env["oracle"]
+    from paper_1703_09619_amd import learned_k
+    meta = json.load(open(os.path.splitext(MODEL)[0] + ".json"))
+    ctx.mlp_load(MODEL)
+    w = W.make("scalar_planewave", E=4096, seed=W.BASE_SEED + 99)
+    ev = learned_k.evaluate(ctx, w, meta["p_cover"], meta["theta"], 1e-8, reps=2)
+    print("evaluation", ev, flush=True)
+    assert ev["max_err"] <= 1e-8
+    assert ev["speedup"] > 1.0
+    plan, out, st = learned_k.learned_fill(ctx, W.subset(w, np.arange(2)), meta["p_cover"], meta["theta"])
+    rules = plan.rules()
+    sub = W.subset(w, np.arange(2))
+    ref, roff, _ = oracle.fill(sub.problem, sub.material, sub.nodes, sub.mat, sub.orders, rules)
+    g = out.cpu().numpy()
+    for e in range(2):
+        x, y = g[roff[e]:roff[e + 1]], ref[roff[e]:roff[e + 1]]
+        assert np.linalg.norm(x - y) / np.linalg.norm(y) <= 1e-10
