@@ -32,8 +32,11 @@ WORKLOADS = {
     "scalar_n4": "scalar diffusion+mass, N=4 (64 dofs), 64 elements, 8^3 points, node noise 0.1",
     "scalar_mixed": "scalar diffusion+mass, N~U{2..8}, Q=2N, 20000 elements, node noise 0.1",
     "vector_n8": "vector curl-curl+mass, N=8 (1344 dofs), 8192 elements, 16^3 points",
+    "scalar_planewave": "scalar diffusion+mass, N=6 (216 dofs), 50000 elements, eps = 1 + 0.8 sin(k.x+phase), "
+                        "|k| log-uniform in [0.5,16] pi, node noise U[0,0.3]; Gauss rule per axis chosen by the "
+                        "learned order (full rule 24^3, tail check with fallback)",
 }
-CPU_SAMPLE = {"vector_n6": 24, "scalar_n4": 64, "scalar_mixed": 40, "vector_n8": 4}
+CPU_SAMPLE = {"vector_n6": 24, "scalar_n4": 64, "scalar_mixed": 40, "vector_n8": 4, "scalar_planewave": 6}
 
 
 def contract_bytes_per_element(problem: int, N: int) -> int:
@@ -80,6 +83,14 @@ def main():
     dev = torch.device("cuda", 0)
     ctx = p2s.Context(0)
     plan = ctx.plan(w.problem, w.material, w.orders, w.quad)
+    learned = None
+    if args.workload == "scalar_planewave":
+        from paper_1703_09619_amd import learned_k
+        meta = json.load(open(os.path.splitext(learned_k.DEFAULT_MODEL)[0] + ".json"))
+        ctx.mlp_init(0, 1)
+        ctx.mlp_load(learned_k.DEFAULT_MODEL)
+        plan.set_learned(True, meta["p_cover"], meta["theta"], meta.get("k_direct", p2s.KMAX + 1))
+        learned = meta
     nodes = torch.from_numpy(w.nodes).to(dev)
     mat = torch.from_numpy(w.mat).to(dev)
     out = torch.empty(int(plan.offsets[-1]), dtype=torch.float64, device=dev)
@@ -122,6 +133,27 @@ def main():
                 "kernel": "k_contract", "avg_launch_ms": round(c_ms / max(c_launches, 1), 4),
                 "launches_per_step": c_launches // args.steps}
 
+    if learned is not None:
+        # the same plan without the network (full rule on every axis)
+        ref = torch.empty_like(out)
+        rst = torch.empty_like(status)
+        stn = st
+        rules = plan.rules()
+        plan.set_learned(False)
+        plan.execute(nodes, mat, ref, rst)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.execute(nodes, mat, ref, rst)
+        torch.cuda.synchronize()
+        f1 = time.perf_counter()
+        err = ctx.rel_error(out, ref, offsets=torch.from_numpy(plan.offsets).to(dev)).cpu().numpy()
+        learned.update(full_rule_elements_per_s=round(w.E / ((f1 - f0) / args.steps), 1),
+                       speedup=round(((f1 - f0) / args.steps) / (ms_per_step * 1e-3), 3),
+                       max_rel_err_vs_full_rule=float(err.max()),
+                       fallback_rate=float(((stn & 4) != 0).mean()), mean_points=float(np.prod(rules, 1).mean()))
+        del ref
+
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "element matrices/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -133,6 +165,8 @@ def main():
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "status_nonzero": int((st != 0).sum()),
     }
+    if learned is not None:
+        result["learned_order"] = learned
 
     if args.direct_elements > 0 and len(set(w.orders.tolist())) == 1:
         # the method the paper compares against, on the GPU: direct quadrature

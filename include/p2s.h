@@ -110,7 +110,7 @@ typedef struct {
 #define P2S_STATUS_DETJ 1u      /* det J <= 0 at some Gauss point          */
 #define P2S_STATUS_NONFINITE 2u /* non-finite value in the element matrix */
 #define P2S_STATUS_FALLBACK 4u  /* learned order rejected, refilled at max */
-#define P2S_STATUS_TAIL 8u      /* tail check still above tolerance        */
+#define P2S_STATUS_TAIL 8u      /* reserved (not set)                      */
 
 /* Create a context on HIP device `device`: checks that it is gfx950,
  * builds the FP64 tables (Gauss rules up to P2S_MAX_Q points, Legendre
@@ -228,14 +228,31 @@ int p2s_mlp_train_step(p2s_ctx ctx, int64_t B, const float *x, const int32_t *la
 int p2s_mlp_predict(p2s_ctx ctx, int64_t B, const float *x, float p_cover, int32_t *quad, void *stream);
 /* Learned mode of a plan created with P2S_KMAX points on every axis (so its
  * workspace holds the full rule): each execution computes the features,
- * runs the network, samples the coupling factor with the chosen rules,
- * and checks the tail: along each axis the Legendre coefficients of the two
- * highest degrees the rule resolves, over all lines of points and fields,
- * relative to the largest coupling value; above theta the element is
- * sampled again with the full rule (status P2S_STATUS_FALLBACK; still above
- * theta afterwards: P2S_STATUS_TAIL).  Allocates its workspace here;
+ * runs the network, chooses per axis the smallest K whose predicted
+ * cumulative probability reaches p_cover (K >= k_direct: the full rule at
+ * once; k_direct > P2S_KMAX disables that), samples the coupling factor with
+ * the chosen rules and checks the tail.  Along each axis the moment stage takes, on every line it
+ * contracts (samples for w, w-moments for v, (v,w)-moments for u), the
+ * discrete Legendre coefficients of the four highest degrees the rule
+ * resolves; their decay extrapolated to the first degree the moments of
+ * eq. (4) can alias, relative to the largest value of that tensor, is the
+ * axis statistic.  Its maximum over the axes sampled below the full rule is
+ * the element's tail value; above theta the element is sampled again with
+ * the full rule (status P2S_STATUS_FALLBACK).  Axes already at the full
+ * rule take no statistic.  Allocates its workspace here;
  * enable = 0 restores the plan's own rules. */
-int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, double theta);
+int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, int k_direct, double theta);
+/* Tail records of the moment stage at the plan's own rules (coupling and
+ * moments only; no contraction): records [device][E][F][16], per field
+ * env[axis][j] at axis*4+j, j = 0..3 for the degrees Q-1..Q-4 of that axis
+ * (axis 0 = u on the (v,w)-moments, 1 = v on the w-moments, 2 = w on the
+ * samples), and the largest magnitude of the tensor each axis was examined
+ * on at 12+axis; entry 15 is zero, and so is every entry of an axis sampled
+ * with P2S_KMAX points or more.  The statistic of p2s_plan_set_learned
+ * is computed from these.  Product-to-sum plans; allocates its workspace on
+ * first use. */
+int p2s_plan_tail_records(p2s_plan plan, const double *nodes, const double *material, double *records,
+                          void *stream);
 /* Rules used by the last execution: quad [host][E][3]. */
 int p2s_plan_rules(p2s_plan plan, int32_t *quad);
 /* Tail statistic of each element at its predicted rule in the last learned

@@ -37,6 +37,7 @@ EXPORTS = (
     "p2s_plan_replay", "p2s_mlp_init", "p2s_mlp_set_params", "p2s_mlp_get_params", "p2s_mlp_save",
     "p2s_mlp_load", "p2s_features", "p2s_mlp_forward", "p2s_mlp_gradients", "p2s_mlp_train_step",
     "p2s_mlp_predict", "p2s_plan_set_learned", "p2s_plan_rules", "p2s_rel_error", "p2s_plan_tail_values",
+    "p2s_plan_tail_records",
 )
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 85, 128, 57, 34873
 KMIN, KMAX = 6, 24
@@ -97,9 +98,10 @@ def load():
         lib.p2s_mlp_gradients.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         lib.p2s_mlp_train_step.argtypes = [vp, i64, vp, vp, ctypes.c_float, vp, vp]
         lib.p2s_mlp_predict.argtypes = [vp, i64, vp, ctypes.c_float, vp, vp]
-        lib.p2s_plan_set_learned.argtypes = [vp, i32, ctypes.c_float, d]
+        lib.p2s_plan_set_learned.argtypes = [vp, i32, ctypes.c_float, i32, d]
         lib.p2s_plan_rules.argtypes = [vp, vp]
         lib.p2s_plan_tail_values.argtypes = [vp, vp]
+        lib.p2s_plan_tail_records.argtypes = [vp, vp, vp, vp, vp]
         lib.p2s_rel_error.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
         lib.p2s_gauss_rule.argtypes = [i32, vp, vp]
         lib.p2s_linearization.argtypes = [i32, i32, i32, i32, vp]
@@ -110,7 +112,7 @@ def load():
                   "p2s_plan_replay", "p2s_mlp_init", "p2s_mlp_set_params", "p2s_mlp_get_params",
                   "p2s_mlp_save", "p2s_mlp_load", "p2s_features", "p2s_mlp_forward", "p2s_mlp_gradients",
                   "p2s_mlp_train_step", "p2s_mlp_predict", "p2s_plan_set_learned", "p2s_plan_rules",
-                  "p2s_rel_error", "p2s_plan_tail_values"):
+                  "p2s_rel_error", "p2s_plan_tail_values", "p2s_plan_tail_records"):
             getattr(lib, f).restype = i32
         _lib = lib
     return _lib
@@ -183,6 +185,15 @@ class Context:
     def check(self, rc: int, what: str):
         if rc != 0:
             raise P2SError("%s failed (%d): %s" % (what, rc, self.error()))
+
+    def tail_records(self, nodes, material, stream=None):
+        """[E][F][16] tail records of the moment stage at the plan's rules."""
+        import torch
+        F = 7 if self.terms.problem == SCALAR else 12
+        r = torch.zeros(self.E * F * 16, dtype=torch.float64, device=torch.device("cuda", self.ctx.device))
+        rc = load().p2s_plan_tail_records(self._h, _dev_ptr(nodes), _dev_ptr(material), _dev_ptr(r), _stream(stream))
+        self.ctx.check(rc, "p2s_plan_tail_records")
+        return r.view(self.E, F, 16)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -337,9 +348,9 @@ class Plan:
     def replay(self, stream=None):
         self.ctx.check(load().p2s_plan_replay(self._h, _stream(stream)), "p2s_plan_replay")
 
-    def set_learned(self, enable=True, p_cover=0.99, theta=1e-9):
-        self.ctx.check(load().p2s_plan_set_learned(self._h, int(enable), float(p_cover), float(theta)),
-                       "p2s_plan_set_learned")
+    def set_learned(self, enable=True, p_cover=0.99, theta=1e-9, k_direct=KMAX + 1):
+        self.ctx.check(load().p2s_plan_set_learned(self._h, int(enable), float(p_cover), int(k_direct),
+                                                   float(theta)), "p2s_plan_set_learned")
 
     def tail_values(self) -> np.ndarray:
         t = np.zeros(self.E)
@@ -368,6 +379,15 @@ class Plan:
         rc = load().p2s_plan_moments(self._h, _dev_ptr(nodes), _dev_ptr(material), _dev_ptr(m), _stream(stream))
         self.ctx.check(rc, "p2s_plan_moments")
         return m.view(self.E, F, K, K, K)
+
+    def tail_records(self, nodes, material, stream=None):
+        """[E][F][16] tail records of the moment stage at the plan's rules."""
+        import torch
+        F = 7 if self.terms.problem == SCALAR else 12
+        r = torch.zeros(self.E * F * 16, dtype=torch.float64, device=torch.device("cuda", self.ctx.device))
+        rc = load().p2s_plan_tail_records(self._h, _dev_ptr(nodes), _dev_ptr(material), _dev_ptr(r), _stream(stream))
+        self.ctx.check(rc, "p2s_plan_tail_records")
+        return r.view(self.E, F, 16)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -71,10 +71,12 @@ struct p2s_plan_s {
     // learned quadrature order
     bool learned = false;
     float p_cover = 0.99f;
+    int k_direct = MLP_KMAX + 1;
     double theta = 1e-9;
     float *d_lx = nullptr, *d_lh1 = nullptr, *d_lh2 = nullptr, *d_lz = nullptr;
     int32_t *d_redo = nullptr;
-    double *d_tau = nullptr;  // tail statistic of the last learned execution
+    double *d_tau = nullptr;     // tail statistic of the last learned execution
+    double *d_tailst = nullptr;  // [E][F][TAIL_REC] records of the moment stage
     std::vector<ElemDesc> desc_host;
     // captured execution
     hipGraph_t graph = nullptr;
@@ -231,6 +233,7 @@ void p2s_plan_destroy(p2s_plan plan)
     hipFree(plan->d_lz);
     hipFree(plan->d_redo);
     hipFree(plan->d_tau);
+    hipFree(plan->d_tailst);
     if (plan->gexec) hipGraphExecDestroy(plan->gexec);
     if (plan->graph) hipGraphDestroy(plan->graph);
     for (auto &v : plan->ev)
@@ -430,7 +433,7 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
     return P2S_OK;
 }
 
-enum StageStop { STOP_COUPLING = 0, STOP_MOMENTS = 1, STOP_FULL = 2 };
+enum StageStop { STOP_COUPLING = 0, STOP_MOMENTS = 1, STOP_FULL = 2, STOP_TAILREC = 3 };
 
 static int run_plan(p2s_plan plan, const double *nodes, const double *material, double *out,
                     uint32_t *status, hipStream_t st, int stop, double *stage_out)
@@ -450,7 +453,7 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         prof_begin(plan, 3, st);
         launch_features(plan->E, nodes, material, plan->terms.material, plan->mat_stride, plan->d_lx, st);
         launch_mlp_forward(plan->E, ctx->d_mlp, plan->d_lx, plan->d_lh1, plan->d_lh2, plan->d_lz, st);
-        launch_choose(plan->E, plan->d_lz, plan->p_cover, nullptr, plan->d_desc, st);
+        launch_choose(plan->E, plan->d_lz, plan->p_cover, plan->k_direct, nullptr, plan->d_desc, st);
         prof_end(plan, 3, st);
     }
     for (const Chunk &c : plan->chunks) {
@@ -473,19 +476,19 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         }
         prof_begin(plan, 1, st);
         launch_moments(problem, plan->maxN, plan->maxQu, plan->maxQuv, plan->d_desc, c.e0, c.count,
-                       plan->d_alpha, ctx->d_tab, plan->d_mom, nullptr, st);
+                       plan->d_alpha, ctx->d_tab, plan->d_mom, nullptr,
+                       (learned || stop == STOP_TAILREC) ? plan->d_tailst : nullptr, st);
         prof_end(plan, 1, st);
+        if (stop == STOP_TAILREC) continue;
         if (learned) {
             // tail check; rejected elements are sampled again with the full rule
             prof_begin(plan, 3, st);
-            launch_tail(plan->d_desc, c.e0, c.count, F, plan->d_alpha, ctx->d_tab, plan->theta, MLP_KMAX, 0,
-                        plan->d_redo, status, plan->d_tau, st);
+            launch_tail_decide(plan->d_desc, c.e0, c.count, F, plan->d_tailst, plan->theta, MLP_KMAX,
+                               plan->d_redo, status, plan->d_tau, st);
             launch_coupling(problem, plan->d_desc, c.e0, c.count, nodes, material, plan->terms.material,
                             plan->mat_stride, ctx->d_tab, plan->d_alpha, status, plan->d_redo, st);
             launch_moments(problem, plan->maxN, plan->maxQu, plan->maxQuv, plan->d_desc, c.e0, c.count,
-                           plan->d_alpha, ctx->d_tab, plan->d_mom, plan->d_redo, st);
-            launch_tail(plan->d_desc, c.e0, c.count, F, plan->d_alpha, ctx->d_tab, plan->theta, MLP_KMAX, 1,
-                        plan->d_redo, status, nullptr, st);
+                           plan->d_alpha, ctx->d_tab, plan->d_mom, plan->d_redo, nullptr, st);
             prof_end(plan, 3, st);
         }
         if (stop == STOP_MOMENTS) {
@@ -511,6 +514,9 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         }
         prof_end(plan, 2, st);
     }
+    if (stop == STOP_TAILREC)
+        HIP_TRY(ctx, hipMemcpyAsync(stage_out, plan->d_tailst, sizeof(double) * plan->E * F * TAIL_REC,
+                                    hipMemcpyDeviceToDevice, st));
     HIP_TRY(ctx, hipGetLastError());
     return P2S_OK;
 }
@@ -562,6 +568,23 @@ int p2s_plan_moments(p2s_plan plan, const double *nodes, const double *material,
     if (!plan->uniform) return fail(plan->ctx, P2S_EINVAL, "moment output needs a uniform plan");
     return run_plan(plan, nodes, material, nullptr, plan->d_stage_status, (hipStream_t)stream, STOP_MOMENTS,
                     moments);
+}
+
+int p2s_plan_tail_records(p2s_plan plan, const double *nodes, const double *material, double *records,
+                          void *stream)
+{
+    if (!plan) return P2S_EINVAL;
+    p2s_ctx ctx = plan->ctx;
+    if (plan->terms.method != P2S_METHOD_P2S) return fail(ctx, P2S_EINVAL, "tail records need the product-to-sum method");
+    if (plan->E > 0 && !plan->d_tailst) {
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        const int64_t n = plan->E * num_fields(plan->terms.problem) * TAIL_REC;
+        if (hipMalloc(&plan->d_tailst, sizeof(double) * n) != hipSuccess)
+            return fail(ctx, P2S_ENOMEM, "tail records: workspace allocation failed");
+        plan->bytes += 8 * n;
+    }
+    return run_plan(plan, nodes, material, nullptr, plan->d_stage_status, (hipStream_t)stream, STOP_TAILREC,
+                    records);
 }
 
 int p2s_fill_element_matrices(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const double *nodes,
@@ -932,12 +955,12 @@ int p2s_mlp_predict(p2s_ctx ctx, int64_t B, const float *x, float p_cover, int32
     if (r != P2S_OK) return r;
     hipStream_t st = (hipStream_t)stream;
     launch_mlp_forward(B, ctx->d_mlp, x, ctx->d_h1, ctx->d_h2, ctx->d_z, st);
-    launch_choose(B, ctx->d_z, p_cover, quad, nullptr, st);
+    launch_choose(B, ctx->d_z, p_cover, MLP_KMAX + 1, quad, nullptr, st);
     HIP_TRY(ctx, hipGetLastError());
     return P2S_OK;
 }
 
-int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, double theta)
+int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, int k_direct, double theta)
 {
     if (!plan) return P2S_EINVAL;
     p2s_ctx ctx = plan->ctx;
@@ -953,7 +976,8 @@ int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, double theta)
         plan->Qu != MLP_KMAX || plan->Qv != MLP_KMAX || plan->Qw != MLP_KMAX)
         return fail(ctx, P2S_EINVAL, "learned order: needs a uniform product-to-sum plan created with %d points "
                                      "per axis", MLP_KMAX);
-    if (!(p_cover > 0.f && p_cover <= 1.f) || !(theta > 0.0)) return fail(ctx, P2S_EINVAL, "learned order: bad p/theta");
+    if (!(p_cover > 0.f && p_cover <= 1.f) || !(theta > 0.0) || k_direct < MLP_KMIN)
+        return fail(ctx, P2S_EINVAL, "learned order: bad p_cover / k_direct / theta");
     if (!plan->d_lx && plan->E > 0) {
         const int64_t E = plan->E;
         bool ok = hipMalloc(&plan->d_lx, sizeof(float) * E * MLP_IN) == hipSuccess &&
@@ -961,12 +985,17 @@ int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, double theta)
                   hipMalloc(&plan->d_lh2, sizeof(float) * E * MLP_H) == hipSuccess &&
                   hipMalloc(&plan->d_lz, sizeof(float) * E * MLP_OUT) == hipSuccess &&
                   hipMalloc(&plan->d_redo, sizeof(int32_t) * E) == hipSuccess &&
-                  hipMalloc(&plan->d_tau, sizeof(double) * E) == hipSuccess;
+                  hipMalloc(&plan->d_tau, sizeof(double) * E) == hipSuccess &&
+                  (plan->d_tailst || hipMalloc(&plan->d_tailst, sizeof(double) * E *
+                                                                    num_fields(plan->terms.problem) * TAIL_REC) ==
+                                         hipSuccess);
         if (!ok) return fail(ctx, P2S_ENOMEM, "learned order: workspace allocation failed");
-        plan->bytes += E * (int64_t)(4 * (MLP_IN + 2 * MLP_H + MLP_OUT) + 12);
+        plan->bytes += E * (int64_t)(4 * (MLP_IN + 2 * MLP_H + MLP_OUT) + 12 +
+                                     8 * num_fields(plan->terms.problem) * TAIL_REC);
     }
     plan->learned = true;
     plan->p_cover = p_cover;
+    plan->k_direct = k_direct;
     plan->theta = theta;
     return P2S_OK;
 }

@@ -102,7 +102,16 @@ constexpr int TAB_PACK = TAB_LEGW + LEGW_SIZE;
 // basis[Q][family][m][a] for family in {phi, phi', psi}
 constexpr int BASIS_STRIDE_Q = NFAM * MAXN * MAXQ;
 constexpr int TAB_BASIS = TAB_PACK + PACKED_SIZE;
-constexpr int TAB_SIZE = TAB_BASIS + (MAXQ + 1) * BASIS_STRIDE_Q;
+// Tail rows of the learned-order check: for each Q, the discrete Legendre
+// coefficient weights of the four highest degrees a Q-point rule resolves,
+// tailw[Q][j][a] = (2d+1)/2 w_a L_d(x_a), d = Q-1-j (zero when d < 0).
+constexpr int TAILW_STRIDE_Q = 4 * MAXQ;
+constexpr int TAB_TAILW = TAB_BASIS + (MAXQ + 1) * BASIS_STRIDE_Q;
+constexpr int TAB_SIZE = TAB_TAILW + (MAXQ + 1) * TAILW_STRIDE_Q;
+// Per (element, field) tail record written by the moment stage in learned
+// mode: env[axis][j] at axis*4+j (axis 0 = u, 1 = v, 2 = w), the scale of
+// the tensor the axis was examined on at 12+axis.
+constexpr int TAIL_REC = 16;
 
 // Mirrors of the public enums and status bits (include/p2s.h).
 enum MatKind : int { MAT_SINCOSEXP = 0, MAT_ROTDIAG = 1, MAT_PLANEWAVE = 2, ALPHA_SAMPLED = 3 };

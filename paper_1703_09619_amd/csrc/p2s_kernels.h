@@ -20,7 +20,7 @@ void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t coun
                      const double *tab, double *alpha, uint32_t *status, const int32_t *only, hipStream_t st);
 void launch_moments(int problem, int maxN, int maxQu, int maxQuv, const ElemDesc *desc, int64_t e0,
                     int64_t count, const double *alpha, const double *tab, double *mom, const int32_t *only,
-                    hipStream_t st);
+                    double *tailst, hipStream_t st);
 int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0,
                     int64_t count, const double *tab, const double *mom, double *out, uint32_t *status,
                     double sK, double sM, hipStream_t st);
@@ -43,9 +43,10 @@ void launch_mlp_backward(int64_t B, const float *params, const float *X, const f
                          const float *Z, const int32_t *labels, float *dZ, float *dH2, float *dH1, float *grad,
                          float *loss_b, float *loss, hipStream_t st);
 void launch_adam(float *params, const float *grad, float *m, float *v, float lr, int step, hipStream_t st);
-void launch_choose(int64_t E, const float *Z, float p_cover, int32_t *quad, ElemDesc *desc, hipStream_t st);
-void launch_tail(ElemDesc *desc, int64_t e0, int64_t count, int F, const double *alpha, const double *tab,
-                 double theta, int qfull, int mode, int32_t *redo, uint32_t *status, double *tau, hipStream_t st);
+void launch_choose(int64_t E, const float *Z, float p_cover, int k_direct, int32_t *quad, ElemDesc *desc,
+                   hipStream_t st);
+void launch_tail_decide(ElemDesc *desc, int64_t e0, int64_t count, int F, const double *tailst, double theta,
+                        int qfull, int32_t *redo, uint32_t *status, double *tau, hipStream_t st);
 void launch_rel_error(int64_t E, int64_t len, const int64_t *off, const double *a, const double *b, double *err,
                       hipStream_t st);
 

@@ -194,11 +194,25 @@ __global__ __launch_bounds__(256) void k_coupling(const ElemDesc *__restrict__ d
 // with W[k][a] = w_a L_k(x_a), as three passes (contract w, then v, then u).
 // One workgroup per (element, field); the sizes are runtime, the degree
 // count K = 2N-1 selects a register-blocked instantiation.
+//
+// TAIL (learned order): each pass whose axis is sampled below the full
+// rule MLP_KMAX also takes, on every line it contracts, the discrete
+// Legendre coefficients of the four highest degrees its rule resolves (w on
+// the samples, v on the w-moments, u on the (v,w)-moments), keeps their
+// largest magnitudes and the largest magnitude of the tensor it reads, and
+// writes them as the (element, field) tail record (zeros for full axes).
 
-template <int K>
-__device__ void moments_body(const ElemDesc &d, int f, int F, const double *__restrict__ alpha,
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int K, bool TAIL>
+__device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const double *__restrict__ alpha,
                              const double *__restrict__ tab, double *__restrict__ mom, double *sm,
-                             int p2off)
+                             int p2off, double *__restrict__ tailst)
 {
     const int Qu = d.Qu, Qv = d.Qv, Qw = d.Qw;
     const int P = Qu * Qv * Qw;
@@ -206,13 +220,21 @@ __device__ void moments_body(const ElemDesc &d, int f, int F, const double *__re
     const double *Wu = tab + TAB_LEGW + Qu * LEGW_STRIDE_Q;
     const double *Wv = tab + TAB_LEGW + Qv * LEGW_STRIDE_Q;
     const double *Ww = tab + TAB_LEGW + Qw * LEGW_STRIDE_Q;
+    const double *Tu = tab + TAB_TAILW + Qu * TAILW_STRIDE_Q;
+    const double *Tv = tab + TAB_TAILW + Qv * TAILW_STRIDE_Q;
+    const double *Tw = tab + TAB_TAILW + Qw * TAILW_STRIDE_Q;
     constexpr int KS = K + 1;  // LDS row stride
     double *P1 = sm;          // [Qu*Qv][KS]   (q)
     double *P2 = sm + p2off;  // [Qu][K][KS]   (l, q)
     const int tid = threadIdx.x, nt = blockDim.x;
+    double rec[TAIL_REC];
+#pragma unroll
+    for (int i = 0; i < TAIL_REC; ++i) rec[i] = 0.0;
+    // workgroup-uniform: which axes take the tail statistic
+    const bool tu = TAIL && Qu < MLP_KMAX, tv = TAIL && Qv < MLP_KMAX, tw = TAIL && Qw < MLP_KMAX;
     // pass 1: contract w
     for (int ab = tid; ab < Qu * Qv; ab += nt) {
-        double acc[K];
+        double acc[K], tl[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < K; ++q) acc[q] = 0.0;
         const double *Ar = A + (int64_t)ab * Qw;
@@ -220,7 +242,15 @@ __device__ void moments_body(const ElemDesc &d, int f, int F, const double *__re
             const double x = Ar[c];
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] = fma(Ww[q * MAXQ + c], x, acc[q]);
+            if (tw) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) tl[j] = fma(Tw[j * MAXQ + c], x, tl[j]);
+                rec[14] = fmax(rec[14], fabs(x));
+            }
         }
+        if (tw)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) rec[8 + j] = fmax(rec[8 + j], fabs(tl[j]));
 #pragma unroll
         for (int q = 0; q < K; ++q) P1[ab * KS + q] = acc[q];
     }
@@ -228,14 +258,22 @@ __device__ void moments_body(const ElemDesc &d, int f, int F, const double *__re
     // pass 2: contract v
     for (int aq = tid; aq < Qu * K; aq += nt) {
         const int a = aq / K, q = aq - (aq / K) * K;
-        double acc[K];
+        double acc[K], tl[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int l = 0; l < K; ++l) acc[l] = 0.0;
         for (int b = 0; b < Qv; ++b) {
             const double x = P1[(a * Qv + b) * KS + q];
 #pragma unroll
             for (int l = 0; l < K; ++l) acc[l] = fma(Wv[l * MAXQ + b], x, acc[l]);
+            if (tv) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) tl[j] = fma(Tv[j * MAXQ + b], x, tl[j]);
+                rec[13] = fmax(rec[13], fabs(x));
+            }
         }
+        if (tv)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) rec[4 + j] = fmax(rec[4 + j], fabs(tl[j]));
 #pragma unroll
         for (int l = 0; l < K; ++l) P2[(a * K + l) * KS + q] = acc[l];
     }
@@ -244,37 +282,63 @@ __device__ void moments_body(const ElemDesc &d, int f, int F, const double *__re
     double *I = mom + d.mom_off + (int64_t)f * K * K * K;
     for (int lq = tid; lq < K * K; lq += nt) {
         const int l = lq / K, q = lq - (lq / K) * K;
-        double acc[K];
+        double acc[K], tl[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < K; ++k) acc[k] = 0.0;
         for (int a = 0; a < Qu; ++a) {
             const double x = P2[(a * K + l) * KS + q];
 #pragma unroll
             for (int k = 0; k < K; ++k) acc[k] = fma(Wu[k * MAXQ + a], x, acc[k]);
+            if (tu) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) tl[j] = fma(Tu[j * MAXQ + a], x, tl[j]);
+                rec[12] = fmax(rec[12], fabs(x));
+            }
         }
+        if (tu)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) rec[j] = fmax(rec[j], fabs(tl[j]));
 #pragma unroll
         for (int k = 0; k < K; ++k) I[k * K * K + lq] = acc[k];
     }
+    if (TAIL) {
+        // block-wide maximum of the record: waves, then LDS (P1 is free now)
+        __syncthreads();
+        const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+        for (int i = 0; i < 15; ++i) {
+            const double v = wave_max(rec[i]);
+            if (lane == 0) sm[wave * TAIL_REC + i] = v;
+        }
+        __syncthreads();
+        if (tid < 15) {
+            double v = 0.0;
+            for (int w = 0; w < (nt + 63) / 64; ++w) v = fmax(v, sm[w * TAIL_REC + tid]);
+            tailst[(e * F + f) * TAIL_REC + tid] = v;
+        }
+    }
 }
 
+template <bool TAIL>
 __global__ __launch_bounds__(256) void k_moments(const ElemDesc *__restrict__ desc, int64_t e0, int F,
                                                  const double *__restrict__ alpha,
                                                  const double *__restrict__ tab,
                                                  double *__restrict__ mom, int p2off,
-                                                 const int32_t *__restrict__ only)
+                                                 const int32_t *__restrict__ only, double *__restrict__ tailst)
 {
     extern __shared__ double sm[];
-    if (only && !only[e0 + blockIdx.x]) return;
-    const ElemDesc d = desc[e0 + blockIdx.x];
+    const int64_t e = e0 + blockIdx.x;
+    if (only && !only[e]) return;
+    const ElemDesc d = desc[e];
     const int f = blockIdx.y;
     switch (d.N) {
-    case 2: moments_body<3>(d, f, F, alpha, tab, mom, sm, p2off); break;
-    case 3: moments_body<5>(d, f, F, alpha, tab, mom, sm, p2off); break;
-    case 4: moments_body<7>(d, f, F, alpha, tab, mom, sm, p2off); break;
-    case 5: moments_body<9>(d, f, F, alpha, tab, mom, sm, p2off); break;
-    case 6: moments_body<11>(d, f, F, alpha, tab, mom, sm, p2off); break;
-    case 7: moments_body<13>(d, f, F, alpha, tab, mom, sm, p2off); break;
-    case 8: moments_body<15>(d, f, F, alpha, tab, mom, sm, p2off); break;
+    case 2: moments_body<3, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
+    case 3: moments_body<5, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
+    case 4: moments_body<7, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
+    case 5: moments_body<9, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
+    case 6: moments_body<11, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
+    case 7: moments_body<13, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
+    case 8: moments_body<15, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
     default: break;
     }
 }
@@ -306,21 +370,28 @@ void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t coun
 
 void launch_moments(int problem, int maxN, int maxQu, int maxQuv, const ElemDesc *desc, int64_t e0,
                     int64_t count, const double *alpha, const double *tab, double *mom, const int32_t *only,
-                    hipStream_t st)
+                    double *tailst, hipStream_t st)
 {
     if (count <= 0) return;
     const int F = num_fields(problem);
-    hipLaunchKernelGGL(k_moments, dim3((unsigned)count, F), dim3(256),
-                       moments_smem_bytes(maxN, maxQu, maxQuv), st, desc, e0, F, alpha, tab, mom,
-                       moments_p2_offset(maxN, maxQuv), only);
+    if (tailst)
+        hipLaunchKernelGGL(k_moments<true>, dim3((unsigned)count, F), dim3(256),
+                           moments_smem_bytes(maxN, maxQu, maxQuv), st, desc, e0, F, alpha, tab, mom,
+                           moments_p2_offset(maxN, maxQuv), only, tailst);
+    else
+        hipLaunchKernelGGL(k_moments<false>, dim3((unsigned)count, F), dim3(256),
+                           moments_smem_bytes(maxN, maxQu, maxQuv), st, desc, e0, F, alpha, tab, mom,
+                           moments_p2_offset(maxN, maxQuv), only, tailst);
 }
 
 int prepare_kernels()
 {
     // k_moments may need more than the default 64 KiB of LDS
-    hipError_t r = hipFuncSetAttribute((const void *)k_moments,
+    hipError_t r = hipFuncSetAttribute((const void *)k_moments<false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    return r == hipSuccess ? 0 : -1;
+    hipError_t r2 = hipFuncSetAttribute((const void *)k_moments<true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    return r == hipSuccess && r2 == hipSuccess ? 0 : -1;
 }
 
 }  // namespace p2s

@@ -9,7 +9,8 @@
 // sends elements it does not trust back to the full rule.
 //
 // Everything here runs in these kernels: features, inference, the order
-// choice, the tail check, and training (forward with saved activations,
+// choice, the tail decision (its statistic is gathered by the moment
+// stage), and training (forward with saved activations,
 // softmax cross-entropy backward, weight gradients, Adam).
 #include <hip/hip_runtime.h>
 
@@ -145,10 +146,12 @@ __global__ void k_adam(int P, float *__restrict__ p, const float *__restrict__ g
 }
 
 // Order choice: per element and axis, the smallest K whose cumulative
-// predicted probability reaches p_cover; written to quad[e][3] and, when
-// desc is given, into the element descriptors.
-__global__ void k_choose(int64_t E, const float *__restrict__ Z, float p_cover, int32_t *__restrict__ quad,
-                         ElemDesc *__restrict__ desc)
+// predicted probability reaches p_cover, raised to the full rule MLP_KMAX
+// when it is at least k_direct (an axis the network is that unsure of is
+// sampled with the full rule at once); written to quad[e][3] and, when desc
+// is given, into the element descriptors.
+__global__ void k_choose(int64_t E, const float *__restrict__ Z, float p_cover, int k_direct,
+                         int32_t *__restrict__ quad, ElemDesc *__restrict__ desc)
 {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= E) return;
@@ -168,7 +171,7 @@ __global__ void k_choose(int64_t E, const float *__restrict__ Z, float p_cover, 
                 break;
             }
         }
-        K[ax] = MLP_KMIN + pick;
+        K[ax] = MLP_KMIN + pick >= k_direct ? MLP_KMAX : MLP_KMIN + pick;
         if (quad) quad[e * 3 + ax] = K[ax];
     }
     if (desc) {
@@ -179,109 +182,53 @@ __global__ void k_choose(int64_t E, const float *__restrict__ Z, float p_cover, 
 }
 
 // ---------------------------------------------------------------------------
-// Tail check of the sampled coupling factor.  With Q points along axis x the
-// moment of degree k is exact unless alpha has Legendre content along x at
-// degrees >= 2Q - k; the highest moment degree is K_m - 1 = 2N - 2.  From
-// the samples, the discrete Legendre coefficients of the four highest
-// degrees the rule resolves, d = Q-1 .. Q-4, are taken on every line of
-// points parallel to x,
-//   a_d = (2d+1)/2 sum_a w_a L_d(x_a) alpha(line, a),
-// and their envelope A_j = max over lines and fields of |a_{Q-j}|.  The
-// decay over two degrees, r2 = max(A_1/A_3, A_2/A_4) (at most 1), gives the
-// estimate of the content at degree 2Q - (K_m - 1),
-//   est_x = max(A_1, A_2) * r2^((Q - K_m + 2) / 2),
-// and tau = max over axes of est_x / max|alpha|.
-// mode 0: elements with tau > theta get the full rule (descriptor set to
-// `qfull` on every axis), redo[e] = 1 and the fallback bit; mode 1 (after the
-// refill): elements still above theta get the tail bit.
-__global__ __launch_bounds__(256) void k_tail(ElemDesc *__restrict__ desc, int64_t e0, int F,
-                                              const double *__restrict__ alpha, const double *__restrict__ tab,
-                                              double theta, int qfull, int mode, int32_t *__restrict__ redo,
-                                              uint32_t *__restrict__ status, double *__restrict__ tau_out)
+// Tail check.  With Q points along an axis, the moment of degree k along it
+// is exact unless the integrand has Legendre content along that axis at
+// degrees >= 2Q - k; the highest moment degree is K_m - 1 = 2N - 2.  The
+// moment stage records, per field and axis, the envelope A_j (largest
+// magnitude over the lines it contracts) of the discrete Legendre
+// coefficients of degrees Q-1 .. Q-4 and the scale S (largest magnitude of
+// the tensor those lines come from).  Per axis, over the fields:
+//   r2  = min(1, max(A_1/A_3, A_2/A_4))    (decay over two degrees)
+//   est = max(A_1, A_2) r2^((Q - K_m + 2)/2)  (content at degree 2Q-K_m+1)
+//   t   = est / S.
+// Only axes sampled below the full rule can differ from the full-rule fill
+// (the moment stage records nothing for the others): tau = max of t over
+// those axes.  tau > theta sends the element back to the full rule
+// (redo[e] = 1, descriptor set to `qfull` on every axis, fallback bit).
+__global__ void k_tail_decide(ElemDesc *__restrict__ desc, int64_t e0, int64_t count, int F,
+                              const double *__restrict__ tailst, double theta, int qfull,
+                              int32_t *__restrict__ redo, uint32_t *__restrict__ status,
+                              double *__restrict__ tau_out)
 {
-    const int64_t e = e0 + blockIdx.x;
-    if (mode == 1 && !redo[e]) return;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t e = e0 + i;
     const ElemDesc d = desc[e];
     const int Q[3] = {d.Qu, d.Qv, d.Qw};
     const int Km = 2 * d.N - 1;
-    const int P = Q[0] * Q[1] * Q[2];
-    const double *A = alpha + d.alpha_off;
-    __shared__ double lt[4][MAXQ];  // w_a L_{Q-j}(x_a) (2(Q-j)+1)/2, j = 1..4
-    __shared__ double red[5][256];
-    double scale = 0.0;
-    for (int i = threadIdx.x; i < F * P; i += blockDim.x) scale = fmax(scale, fabs(A[i]));
-    double est = 0.0;  // meaningful in thread 0
+    double tau = 0.0;
     for (int ax = 0; ax < 3; ++ax) {
-        const int q = Q[ax];
-        const double *gx = tab + TAB_GX + q * MAXQ;
-        const double *gw = tab + TAB_GW + q * MAXQ;
-        __syncthreads();
-        if ((int)threadIdx.x < q) {
-            const double t = gx[threadIdx.x];
-            double L[MAXQ + 1];
-            L[0] = 1.0;
-            L[1] = t;
-            for (int k = 2; k < q; ++k) L[k] = ((2 * k - 1) * t * L[k - 1] - (k - 1) * L[k - 2]) / k;
-            for (int j = 1; j <= 4; ++j) {
-                const int dg = q - j;
-                lt[j - 1][threadIdx.x] = dg >= 0 ? gw[threadIdx.x] * L[dg] * (2.0 * dg + 1.0) / 2.0 : 0.0;
-            }
-        }
-        __syncthreads();
-        const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
-        const int strides[3] = {Q[1] * Q[2], Q[2], 1};
-        const int nlines = Q[o1] * Q[o2];
-        double env[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int w = threadIdx.x; w < F * nlines; w += blockDim.x) {
-            const int s = w / nlines, ln = w % nlines;
-            const int i1 = ln / Q[o2], i2 = ln % Q[o2];
-            const double *base = A + (int64_t)s * P + i1 * strides[o1] + i2 * strides[o2];
-            double c[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int a = 0; a < q; ++a) {
-                const double y = base[(int64_t)a * strides[ax]];
+        if (Q[ax] >= qfull) continue;
+        double A[4] = {0.0, 0.0, 0.0, 0.0}, S = 0.0;
+        for (int f = 0; f < F; ++f) {
+            const double *r = tailst + (e * F + f) * TAIL_REC;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) c[j] = fma(lt[j][a], y, c[j]);
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) env[j] = fmax(env[j], fabs(c[j]));
+            for (int j = 0; j < 4; ++j) A[j] = fmax(A[j], r[ax * 4 + j]);
+            S = fmax(S, r[12 + ax]);
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) red[j][threadIdx.x] = env[j];
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) red[j][threadIdx.x] = fmax(red[j][threadIdx.x], red[j][threadIdx.x + w]);
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            const double A1 = red[0][0], A2 = red[1][0], A3 = red[2][0], A4 = red[3][0];
-            double r2 = fmax(A3 > 0.0 ? A1 / A3 : 1.0, A4 > 0.0 ? A2 / A4 : 1.0);
-            r2 = fmin(r2, 1.0);
-            const double expo = 0.5 * (double)(q - Km + 2);
-            const double ex = q < 5 ? fmax(A1, A2) : fmax(A1, A2) * pow(r2, fmax(expo, 0.0));
-            est = fmax(est, ex);
-        }
+        double r2 = fmax(A[2] > 0.0 ? A[0] / A[2] : 1.0, A[3] > 0.0 ? A[1] / A[3] : 1.0);
+        r2 = fmin(r2, 1.0);
+        const double expo = fmax(0.5 * (double)(Q[ax] - Km + 2), 0.0);
+        const double est = fmax(A[0], A[1]) * pow(r2, expo);
+        tau = fmax(tau, est / fmax(S, 1e-300));
     }
-    red[4][threadIdx.x] = scale;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double tau = est / fmax(red[4][0], 1e-300);
-        if (tau_out) tau_out[e] = tau;
-        if (mode == 0) {
-            const bool fail = !(tau <= theta);
-            redo[e] = fail ? 1 : 0;
-            if (fail) {
-                desc[e].Qu = desc[e].Qv = desc[e].Qw = qfull;
-                status[e] |= P2S_STATUS_FALLBACK_BIT;
-            }
-        } else if (!(tau <= theta)) {
-            status[e] |= P2S_STATUS_TAIL_BIT;
-        }
+    if (tau_out) tau_out[e] = tau;
+    const bool fail = !(tau <= theta);
+    redo[e] = fail ? 1 : 0;
+    if (fail) {
+        desc[e].Qu = desc[e].Qv = desc[e].Qw = qfull;
+        status[e] |= P2S_STATUS_FALLBACK_BIT;
     }
 }
 
@@ -364,17 +311,19 @@ void launch_adam(float *params, const float *grad, float *m, float *v, float lr,
                        b2, 1e-8f, c1, c2);
 }
 
-void launch_choose(int64_t E, const float *Z, float p_cover, int32_t *quad, ElemDesc *desc, hipStream_t st)
+void launch_choose(int64_t E, const float *Z, float p_cover, int k_direct, int32_t *quad, ElemDesc *desc,
+                   hipStream_t st)
 {
-    if (E > 0) hipLaunchKernelGGL(k_choose, dim3(nblk(E, 256)), dim3(256), 0, st, E, Z, p_cover, quad, desc);
+    if (E > 0)
+        hipLaunchKernelGGL(k_choose, dim3(nblk(E, 256)), dim3(256), 0, st, E, Z, p_cover, k_direct, quad, desc);
 }
 
-void launch_tail(ElemDesc *desc, int64_t e0, int64_t count, int F, const double *alpha, const double *tab,
-                 double theta, int qfull, int mode, int32_t *redo, uint32_t *status, double *tau, hipStream_t st)
+void launch_tail_decide(ElemDesc *desc, int64_t e0, int64_t count, int F, const double *tailst, double theta,
+                        int qfull, int32_t *redo, uint32_t *status, double *tau, hipStream_t st)
 {
     if (count > 0)
-        hipLaunchKernelGGL(k_tail, dim3((unsigned)count), dim3(256), 0, st, desc, e0, F, alpha, tab, theta, qfull,
-                           mode, redo, status, tau);
+        hipLaunchKernelGGL(k_tail_decide, dim3(nblk(count, 256)), dim3(256), 0, st, desc, e0, count, F, tailst, theta,
+                           qfull, redo, status, tau);
 }
 
 void launch_rel_error(int64_t E, int64_t len, const int64_t *off, const double *a, const double *b, double *err,

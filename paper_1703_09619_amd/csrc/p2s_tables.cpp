@@ -155,6 +155,14 @@ void build_tables(double *tab)
             for (int k = 0; k < KPAD; ++k)
                 tab[TAB_LEGW + Q * LEGW_STRIDE_Q + k * MAXQ + a] = w[a] * L[k];
         }
+        double LL[MAXQ];
+        for (int a = 0; a < Q; ++a) {
+            legendre_values(Q - 1, x[a], LL);
+            for (int j = 0; j < 4; ++j) {
+                const int d = Q - 1 - j;
+                tab[TAB_TAILW + Q * TAILW_STRIDE_Q + j * MAXQ + a] = d >= 0 ? 0.5 * (2 * d + 1) * w[a] * LL[d] : 0.0;
+            }
+        }
     }
 }
 

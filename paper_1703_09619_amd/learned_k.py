@@ -125,74 +125,81 @@ def train(ctx, X, Y, epochs=20, batch=1024, lr=1e-3, seed=0, log=print):
     return hist
 
 
-def learned_fill(ctx, w, p_cover, theta):
+def learned_fill(ctx, w, p_cover, theta, k_direct=KMAX + 1):
     """(plan, out, status) of the learned fill of workload w (rules 24^3)."""
     import torch
     nodes, mat = _dev(w, torch)
     full = np.full((w.E, 3), KMAX, np.int32)
     plan = ctx.plan(w.problem, w.material, w.orders, full)
-    plan.set_learned(True, p_cover, theta)
+    plan.set_learned(True, p_cover, theta, k_direct)
     out, st = plan.execute(nodes, mat)
     return plan, out, st
 
 
-def calibrate_theta(ctx, w, tol, p_cover):
-    """Largest theta with no accepted element above tol on this (held-out)
-    set: run the learned fill with no fallback, compare every element with
-    the full-rule fill, and put theta just below the smallest tail value of
-    an element that misses the tolerance.  Also returns the expected cost
-    (mean Gauss points per element including refills)."""
+def full_fill(ctx, w):
+    """(plan, out, offsets) of the plain full-rule fill of workload w."""
     import torch
-    plan, out, _ = learned_fill(ctx, w, p_cover, 1e300)
-    tau = plan.tail_values()
-    pts = np.prod(plan.rules(), axis=1).astype(np.float64)
     nodes, mat = _dev(w, torch)
     pf = ctx.plan(w.problem, w.material, w.orders, np.full((w.E, 3), KMAX, np.int32))
     ref, _ = pf.execute(nodes, mat)
-    off = torch.from_numpy(pf.offsets).cuda()
+    return pf, ref, torch.from_numpy(pf.offsets).cuda()
+
+
+def calibrate_theta(ctx, w, tol, p_cover, k_direct, ref, off, safety=0.5):
+    """Largest theta (times `safety`) with no accepted element above tol on
+    this held-out set: run the learned fill with no fallback, compare every
+    element with the full-rule fill `ref`, and put theta below the smallest
+    tail value of an element that misses the tolerance.  Also returns the
+    expected cost (mean Gauss points per element including refills)."""
+    plan, out, _ = learned_fill(ctx, w, p_cover, 1e300, k_direct)
+    tau = plan.tail_values()
+    pts = np.prod(plan.rules(), axis=1).astype(np.float64)
     err = ctx.rel_error(out, ref, offsets=off).cpu().numpy()
+    plan.close()
+    del out
     bad = err > tol
-    theta = 0.5 * float(tau[bad].min()) if bad.any() else float(tau.max()) * 2.0
+    theta = safety * float(tau[bad].min()) if bad.any() else max(float(tau.max()) * 2.0, 1e-300)
     back = tau > theta
     cost = float((pts + back * KMAX ** 3).mean())
-    return theta, dict(n=int(w.E), p_cover=p_cover, missed_without_check=int(bad.sum()),
+    return theta, dict(n=int(w.E), p_cover=p_cover, k_direct=k_direct, missed_without_check=int(bad.sum()),
                        fallback_rate=float(back.mean()), max_err_accepted=float(err[~back].max()),
-                       mean_points=float(pts.mean()), cost_points=cost)
+                       mean_points=float(pts.mean()), cost_points=cost, theta=theta)
 
 
-def calibrate(ctx, w, tol, covers=(0.5, 0.7, 0.8, 0.9, 0.95, 0.99)):
-    """Pick (p_cover, theta) with no miss on w and the least expected cost."""
+def calibrate(ctx, w, tol, covers=(0.9, 0.95, 0.99), directs=(16, 18, 20, 22, KMAX + 1)):
+    """Pick (p_cover, k_direct, theta) with no miss on w and the least
+    expected cost."""
+    pf, ref, off = full_fill(ctx, w)
+    pf.close()
     best = None
     rows = []
     for p in covers:
-        theta, info = calibrate_theta(ctx, w, tol, p)
-        rows.append(info)
-        if best is None or info["cost_points"] < best[2]["cost_points"]:
-            best = (p, theta, info)
-    return best[0], best[1], rows
+        for kd in directs:
+            theta, info = calibrate_theta(ctx, w, tol, p, kd, ref, off)
+            rows.append(info)
+            if best is None or info["cost_points"] < best[3]["cost_points"]:
+                best = (p, kd, theta, info)
+    return best[0], best[1], best[2], rows
 
 
-def evaluate(ctx, w, p_cover, theta, tol, reps=3):
+def evaluate(ctx, w, p_cover, theta, tol, k_direct=KMAX + 1, reps=3):
     """Learned fill against the full-rule fill: time, errors, rules."""
     import torch
     nodes, mat = _dev(w, torch)
-    full = np.full((w.E, 3), KMAX, np.int32)
-    pf = ctx.plan(w.problem, w.material, w.orders, full)
-    ref, _ = pf.execute(nodes, mat)
+    pf, ref, off = full_fill(ctx, w)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         pf.execute(nodes, mat, ref)
     torch.cuda.synchronize()
     t_full = (time.perf_counter() - t0) / reps
-    plan, out, st = learned_fill(ctx, w, p_cover, theta)
+    plan, out, st = learned_fill(ctx, w, p_cover, theta, k_direct)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         plan.execute(nodes, mat, out, st)
     torch.cuda.synchronize()
     t_learned = (time.perf_counter() - t0) / reps
-    off = torch.from_numpy(pf.offsets).cuda()
     err = ctx.rel_error(out, ref, offsets=off).cpu().numpy()
     stn = st.cpu().numpy()
     rules = plan.rules()
@@ -205,7 +212,7 @@ def evaluate(ctx, w, p_cover, theta, tol, reps=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=200000, help="training elements")
-    ap.add_argument("--val", type=int, default=8192)
+    ap.add_argument("--val", type=int, default=16384)
     ap.add_argument("--test", type=int, default=50000)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -246,17 +253,17 @@ def main():
                    matrix_moment_ratio=ratio, label_histogram_K6_to_24=hist_labels, loss=hist,
                    label_seconds=t1 - t0, train_seconds=t2 - t1)
     wval = W.make("scalar_planewave", E=args.val, seed=W.BASE_SEED + 41)
-    p_cover, theta, rows = calibrate(ctx, wval, args.tol)
-    log("calibration: p_cover %.2f theta %.3g" % (p_cover, theta))
+    p_cover, k_direct, theta, rows = calibrate(ctx, wval, args.tol)
+    log("calibration: p_cover %.2f k_direct %d theta %.3g" % (p_cover, k_direct, theta))
     for r in rows:
         log("  %s" % r)
     wte = W.make("scalar_planewave", E=args.test)
-    ev = evaluate(ctx, wte, p_cover, theta, args.tol)
+    ev = evaluate(ctx, wte, p_cover, theta, args.tol, k_direct)
     log("evaluation %s" % ev)
-    rep.update(tol=args.tol, p_cover=p_cover, theta=theta, calibration=rows, evaluation=ev)
+    rep.update(tol=args.tol, p_cover=p_cover, k_direct=k_direct, theta=theta, calibration=rows, evaluation=ev)
     meta = os.path.splitext(out_path)[0] + ".json"
     with open(meta, "w") as f:
-        json.dump(dict(p_cover=p_cover, theta=theta, tol=args.tol), f, indent=1)
+        json.dump(dict(p_cover=p_cover, k_direct=k_direct, theta=theta, tol=args.tol), f, indent=1)
     if args.report:
         with open(args.report, "w") as f:
             json.dump(rep, f, indent=1)

@@ -120,28 +120,54 @@ def test_training_reduces_loss(env):
 
 
 def test_learned_fill_forced_fallback_equals_full_rule(env):
-    """theta tiny: every element is sent back to the full rule, and the
-    result equals the plain full-rule fill bit for bit."""
+    """An untrained network has near-uniform class probabilities, so
+    p_cover = 0.05 picks K = 6 on every axis; with theta tiny every element
+    is sent back to the full rule, and the result equals the plain full-rule
+    fill bit for bit."""
     torch, W, ctx, p2s = env["torch"], env["W"], env["ctx"], env["p2s"]
     ctx.mlp_init(seed=13, max_batch=512)
     w = W.make("scalar_planewave", E=96)
     nodes, mat = torch.from_numpy(w.nodes).cuda(), torch.from_numpy(w.mat).cuda()
+    x = ctx.features(w.material, nodes, mat)
+    assert (ctx.mlp_predict(x, 0.05).cpu().numpy() < 24).all()
     full = np.full((w.E, 3), 24, np.int32)
     pf = ctx.plan(w.problem, w.material, w.orders, full)
     ref, rst = pf.execute(nodes, mat)
     pl = ctx.plan(w.problem, w.material, w.orders, full)
-    pl.set_learned(True, 0.99, 1e-300)
+    pl.set_learned(True, 0.05, 1e-300)
     out, st = pl.execute(nodes, mat)
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
     stn = st.cpu().numpy()
     assert ((stn & p2s.STATUS_FALLBACK) != 0).all()
     assert (pl.rules() == 24).all()
+    assert (pl.tail_values() > 0).all()
     # switching learned mode off restores the plan's own rules
     pl.set_learned(False)
     out2, _ = pl.execute(nodes, mat)
     torch.cuda.synchronize()
     assert torch.equal(out2, ref)
+
+
+def test_learned_fill_full_prediction_is_never_refilled(env):
+    """p_cover = 1 picks the full rule on every axis: nothing is below the
+    full rule, so no element falls back (a refill would recompute the same
+    samples) and the result is the full-rule fill."""
+    torch, W, ctx, p2s = env["torch"], env["W"], env["ctx"], env["p2s"]
+    ctx.mlp_init(seed=13, max_batch=512)
+    w = W.make("scalar_planewave", E=64, seed=W.BASE_SEED + 5)
+    nodes, mat = torch.from_numpy(w.nodes).cuda(), torch.from_numpy(w.mat).cuda()
+    full = np.full((w.E, 3), 24, np.int32)
+    ref, _ = ctx.plan(w.problem, w.material, w.orders, full).execute(nodes, mat)
+    pl = ctx.plan(w.problem, w.material, w.orders, full)
+    pl.set_learned(True, 1.0, 1e-300)
+    out, st = pl.execute(nodes, mat)
+    torch.cuda.synchronize()
+    assert (pl.rules() == 24).all()
+    assert torch.equal(out, ref)
+    stn = st.cpu().numpy()
+    assert ((stn & p2s.STATUS_FALLBACK) == 0).all()
+    assert (pl.tail_values() == 0).all()
 
 
 def test_learned_fill_requires_model_and_full_rule(env):
@@ -172,11 +198,12 @@ def test_trained_model_accuracy_and_gain(env):
     meta = json.load(open(os.path.splitext(MODEL)[0] + ".json"))
     ctx.mlp_load(MODEL)
     w = W.make("scalar_planewave", E=4096, seed=W.BASE_SEED + 99)
-    ev = learned_k.evaluate(ctx, w, meta["p_cover"], meta["theta"], 1e-8, reps=2)
+    kd = meta.get("k_direct", 25)
+    ev = learned_k.evaluate(ctx, w, meta["p_cover"], meta["theta"], 1e-8, kd, reps=2)
     print("evaluation", ev, flush=True)
     assert ev["max_err"] <= 1e-8
     assert ev["speedup"] > 1.0
-    plan, out, st = learned_k.learned_fill(ctx, W.subset(w, np.arange(2)), meta["p_cover"], meta["theta"])
+    plan, out, st = learned_k.learned_fill(ctx, W.subset(w, np.arange(2)), meta["p_cover"], meta["theta"], kd)
     rules = plan.rules()
     sub = W.subset(w, np.arange(2))
     ref, roff, _ = oracle.fill(sub.problem, sub.material, sub.nodes, sub.mat, sub.orders, rules)
@@ -184,3 +211,44 @@ def test_trained_model_accuracy_and_gain(env):
     for e in range(2):
         x, y = g[roff[e]:roff[e + 1]], ref[roff[e]:roff[e + 1]]
         assert np.linalg.norm(x - y) / np.linalg.norm(y) <= 1e-10
+
+
+def test_tail_records_and_decision_match_oracle(env):
+    """Tail records of the moment stage and the element tail values against
+    the FP64 reference computed from the oracle's own coupling samples; the
+    fallback decision follows tau > theta element by element."""
+    torch, W, ctx, oracle, p2s = env["torch"], env["W"], env["ctx"], env["oracle"], env["p2s"]
+    from oracle import tail
+    w = W.make("scalar_planewave", E=6, seed=W.BASE_SEED + 7)
+    nodes, mat = torch.from_numpy(w.nodes).cuda(), torch.from_numpy(w.mat).cuda()
+    rules = np.array([[10, 14, 24], [24, 12, 9], [16, 24, 20], [7, 8, 11], [24, 24, 13], [18, 6, 22]], np.int32)
+    rec = ctx.plan(w.problem, w.material, w.orders, rules).tail_records(nodes, mat).cpu().numpy()
+    for e in range(w.E):
+        a = oracle.coupling(w.problem, w.material, w.mat[e], w.nodes[e], *rules[e])
+        ref = tail.records(a, *rules[e], int(w.orders[e]))
+        scale = ref[:, 12:15].max(0)  # per-axis tensor scale
+        for ax in range(3):
+            cols = list(range(4 * ax, 4 * ax + 4)) + [12 + ax]
+            d = np.abs(rec[e][:, cols] - ref[:, cols]).max()
+            assert d <= 1e-13 * max(scale[ax], 1e-300) + 1e-12 * np.abs(ref[:, cols]).max(), (e, ax, d)
+    # learned execution with an untrained network: tail values and decisions
+    ctx.mlp_init(seed=21, max_batch=512)
+    w = W.make("scalar_planewave", E=24, seed=W.BASE_SEED + 8)
+    nodes, mat = torch.from_numpy(w.nodes).cuda(), torch.from_numpy(w.mat).cuda()
+    full = np.full((w.E, 3), 24, np.int32)
+    pl = ctx.plan(w.problem, w.material, w.orders, full)
+    pl.set_learned(True, 0.3, 1e300)
+    pl.execute(nodes, mat)
+    chosen = pl.rules()
+    tau = pl.tail_values()
+    ref_tau = np.array([tail.tail_value(tail.records(
+        oracle.coupling(w.problem, w.material, w.mat[e], w.nodes[e], *chosen[e]), *chosen[e], 6), chosen[e], 6)
+        for e in range(w.E)])
+    assert np.allclose(tau, ref_tau, rtol=1e-9, atol=1e-300)
+    srt = np.sort(ref_tau[ref_tau > 0])
+    theta = float(np.sqrt(srt[len(srt) // 2 - 1] * srt[len(srt) // 2]))  # between two values: no ties
+    pl.set_learned(True, 0.3, theta)
+    _, st = pl.execute(nodes, mat)
+    back = (st.cpu().numpy() & p2s.STATUS_FALLBACK) != 0
+    assert (back == (ref_tau > theta)).all()
+    assert (pl.rules()[back] == 24).all() and (pl.rules()[~back] == chosen[~back]).all()
