@@ -39,13 +39,14 @@ WORKLOADS = {
 CPU_SAMPLE = {"vector_n6": 24, "scalar_n4": 64, "scalar_mixed": 40, "vector_n8": 4, "scalar_planewave": 6}
 
 
-def contract_bytes_per_element(problem: int, N: int) -> int:
+def contract_bytes_per_element(problem: int, N: int, moment_bytes: int = 8) -> int:
     """Algorithmic HBM bytes of the contraction kernel per element: the
-    dense FP64 output block written once plus the moment tensors read once."""
+    dense FP64 output block written once plus the moment tensors read once
+    (FP64, or FP32 in the split form)."""
     nd = N ** 3 if problem == 0 else 3 * (N - 1) * N * N
     F = 7 if problem == 0 else 12
     K = 2 * N - 1
-    return 8 * nd * nd + 8 * F * K ** 3
+    return 8 * nd * nd + moment_bytes * F * K ** 3
 
 
 def cpu_threads() -> int:
@@ -66,6 +67,9 @@ def main():
     ap.add_argument("--direct-elements", type=int, default=64,
                     help="elements of the same workload filled by the GPU direct-quadrature baseline "
                          "(0 = skip)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "split_fp32"],
+                    help="arithmetic of the moment and contraction stages; split_fp32 also times the FP64 "
+                         "path on the same inputs and reports the split error against it")
     ap.add_argument("--copy-probe", action="store_true",
                     help="before the fill, run a plain 1 GiB device copy three times (a known-size "
                          "reference for HBM byte counters)")
@@ -82,7 +86,8 @@ def main():
     w = W.make(args.workload)
     dev = torch.device("cuda", 0)
     ctx = p2s.Context(0)
-    plan = ctx.plan(w.problem, w.material, w.orders, w.quad)
+    split = args.precision == "split_fp32"
+    plan = ctx.plan(w.problem, w.material, w.orders, w.quad, precision=p2s.SPLIT_FP32 if split else p2s.FP64)
     learned = None
     if args.workload == "scalar_planewave":
         from paper_1703_09619_amd import learned_k
@@ -124,13 +129,13 @@ def main():
     if w.problem == 0 and len(set(w.orders.tolist())) > 1:
         alg_bytes = sum(contract_bytes_per_element(0, int(n)) for n in w.orders)
     else:
-        alg_bytes = w.E * contract_bytes_per_element(w.problem, int(w.orders[0]))
+        alg_bytes = w.E * contract_bytes_per_element(w.problem, int(w.orders[0]), 4 if split else 8)
     alg_bytes_per_launch = alg_bytes * args.steps / max(c_launches, 1)
     avg_launch_s = c_ms * 1e-3 / max(c_launches, 1)
     achieved = alg_bytes_per_launch / avg_launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_contract", "avg_launch_ms": round(c_ms / max(c_launches, 1), 4),
+                "kernel": "k_contract_split" if split else "k_contract", "avg_launch_ms": round(c_ms / max(c_launches, 1), 4),
                 "launches_per_step": c_launches // args.steps}
 
     if learned is not None:
@@ -154,10 +159,26 @@ def main():
                        fallback_rate=float(((stn & 4) != 0).mean()), mean_points=float(np.prod(rules, 1).mean()))
         del ref
 
+    precision = None
+    if split:
+        # the same elements through the FP64 path: error on the first 64
+        # elements, then the FP64 rate on the whole batch (into the same buffer,
+        # after the split result has been checked)
+        n64 = min(64, w.E)
+        sub64 = W.subset(w, np.arange(n64))
+        p64 = ctx.plan(sub64.problem, sub64.material, sub64.orders, sub64.quad)
+        o64, _ = p64.execute(torch.from_numpy(sub64.nodes).to(dev), torch.from_numpy(sub64.mat).to(dev))
+        e64 = ctx.rel_error(out[:int(p64.offsets[-1])], o64,
+                            offsets=torch.from_numpy(p64.offsets).to(dev)).cpu().numpy()
+        del o64
+        precision = {"form": "split_fp32", "elements_compared": n64,
+                     "max_rel_err_vs_fp64_gpu": float(e64.max()), "mean_rel_err_vs_fp64_gpu": float(e64.mean())}
+
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "element matrices/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (hi/lo split operands) + f64" if split else "f64",
         "data": "synthetic (seeded curved triquadratic hexahedra and analytic materials)",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "elements": w.E,
                    "orders": sorted(set(int(n) for n in w.orders)), "gauss_points": w.quad[0].tolist()},
@@ -215,6 +236,19 @@ def main():
                                   "sample": "%d seeded elements of the same workload, direct quadrature, "
                                             "FP64, OpenMP over elements" % n}
         result["max_rel_err_vs_oracle"] = max(errs)
+    if precision is not None:
+        del plan
+        p64 = ctx.plan(w.problem, w.material, w.orders, w.quad)
+        p64.execute(nodes, mat, out, status)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        for _ in range(args.steps):
+            p64.execute(nodes, mat, out, status)
+        torch.cuda.synchronize()
+        f1 = time.perf_counter()
+        precision["fp64_elements_per_s"] = round(w.E * args.steps / (f1 - f0), 1)
+        precision["split_speedup_vs_fp64"] = round((f1 - f0) / args.steps / (ms_per_step * 1e-3), 3)
+        result["precision"] = precision
     print(json.dumps(result), flush=True)
 
 

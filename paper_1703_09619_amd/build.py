@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libp2s.so")
 
-HIP_SOURCES = ["p2s_api.hip", "p2s_kernels.hip", "p2s_contract.hip", "p2s_direct.hip", "p2s_learned.hip"]
+HIP_SOURCES = ["p2s_api.hip", "p2s_kernels.hip", "p2s_contract.hip", "p2s_direct.hip", "p2s_learned.hip",
+               "p2s_split.hip"]
 CXX_SOURCES = ["p2s_tables.cpp"]
 ARCH = "gfx950"
 

@@ -26,6 +26,7 @@ using namespace p2s;
 struct p2s_ctx_s {
     int device = 0;
     double *d_tab = nullptr;
+    float *d_tab32 = nullptr;  // hi/lo FP32 split tables of the split-precision path
     std::string err;
     // learned quadrature order: network parameters, Adam state, training scratch
     bool mlp_ready = false;
@@ -196,7 +197,14 @@ int p2s_create(p2s_ctx *out, int device)
         p2s_destroy(ctx);
         return fail(nullptr, P2S_ENOMEM, "p2s_create: table allocation failed");
     }
+    std::vector<float> tab32(T32_SIZE);
+    build_split_tables(tab.data(), tab32.data());
+    if (hipMalloc(&ctx->d_tab32, sizeof(float) * T32_SIZE) != hipSuccess) {
+        p2s_destroy(ctx);
+        return fail(nullptr, P2S_ENOMEM, "p2s_create: table allocation failed");
+    }
     if (hipMemcpy(ctx->d_tab, tab.data(), sizeof(double) * TAB_SIZE, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->d_tab32, tab32.data(), sizeof(float) * T32_SIZE, hipMemcpyHostToDevice) != hipSuccess ||
         prepare_kernels() != 0) {
         p2s_destroy(ctx);
         return fail(nullptr, P2S_EHIP, "p2s_create: table upload failed");
@@ -210,6 +218,7 @@ void p2s_destroy(p2s_ctx ctx)
     if (!ctx) return;
     hipSetDevice(ctx->device);
     if (ctx->d_tab) hipFree(ctx->d_tab);
+    if (ctx->d_tab32) hipFree(ctx->d_tab32);
     for (float *p : {ctx->d_mlp, ctx->d_grad, ctx->d_adam_m, ctx->d_adam_v, ctx->d_h1, ctx->d_h2, ctx->d_z,
                      ctx->d_dz, ctx->d_dh2, ctx->d_dh1, ctx->d_lossb})
         if (p) hipFree(p);
@@ -279,8 +288,10 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
         return fail(ctx, P2S_EINVAL, "plan: the scalar problem takes an isotropic material");
     if (terms->method != P2S_METHOD_P2S && terms->method != P2S_METHOD_DIRECT)
         return fail(ctx, P2S_EINVAL, "plan: bad method %d", terms->method);
-    if (terms->precision != P2S_FP64)
+    if (terms->precision != P2S_FP64 && terms->precision != P2S_SPLIT_FP32)
         return fail(ctx, P2S_EINVAL, "plan: unsupported precision %d", terms->precision);
+    if (terms->precision == P2S_SPLIT_FP32 && terms->method != P2S_METHOD_P2S)
+        return fail(ctx, P2S_EINVAL, "plan: split-FP32 precision is a form of the product-to-sum method");
     auto plan = new p2s_plan_s();
     plan->ctx = ctx;
     plan->terms = *terms;
@@ -324,6 +335,12 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
     if (kind == P2S_ALPHA_SAMPLED && !plan->uniform) {
         delete plan;
         return fail(ctx, P2S_EINVAL, "plan: sampled coupling input needs one order and rule for all elements");
+    }
+    if (terms->precision == P2S_SPLIT_FP32 && E > 0 &&
+        (!plan->uniform || plan->Qu > SPLIT_MAXQ || plan->Qv > SPLIT_MAXQ || plan->Qw > SPLIT_MAXQ)) {
+        delete plan;
+        return fail(ctx, P2S_EQUAD, "plan: split-FP32 precision takes one order and one rule of at most %d points "
+                                    "per axis for all elements", SPLIT_MAXQ);
     }
     if (E > 0 && moments_smem_bytes(plan->maxN, plan->maxQu, plan->maxQuv) > LDS_LIMIT) {
         delete plan;
@@ -474,10 +491,15 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
                                         hipMemcpyDeviceToDevice, st));
             continue;
         }
+        const bool split = plan->terms.precision == P2S_SPLIT_FP32;
         prof_begin(plan, 1, st);
-        launch_moments(problem, plan->maxN, plan->maxQu, plan->maxQuv, plan->d_desc, c.e0, c.count,
-                       plan->d_alpha, ctx->d_tab, plan->d_mom, nullptr,
-                       (learned || stop == STOP_TAILREC) ? plan->d_tailst : nullptr, st);
+        if (split && stop != STOP_TAILREC)
+            launch_moments_split(problem, plan->d_desc, c.e0, c.count, plan->d_alpha, ctx->d_tab32,
+                                 reinterpret_cast<float *>(plan->d_mom), st);
+        else
+            launch_moments(problem, plan->maxN, plan->maxQu, plan->maxQuv, plan->d_desc, c.e0, c.count,
+                           plan->d_alpha, ctx->d_tab, plan->d_mom, nullptr,
+                           (learned || stop == STOP_TAILREC) ? plan->d_tailst : nullptr, st);
         prof_end(plan, 1, st);
         if (stop == STOP_TAILREC) continue;
         if (learned) {
@@ -494,12 +516,19 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         if (stop == STOP_MOMENTS) {
             const int K = 2 * plan->N - 1;
             const int64_t per = (int64_t)F * K * K * K;
-            HIP_TRY(ctx, hipMemcpyAsync(stage_out + c.e0 * per, plan->d_mom, sizeof(double) * per * c.count,
-                                        hipMemcpyDeviceToDevice, st));
+            if (split)
+                launch_widen(per * c.count, reinterpret_cast<const float *>(plan->d_mom), stage_out + c.e0 * per, st);
+            else
+                HIP_TRY(ctx, hipMemcpyAsync(stage_out + c.e0 * per, plan->d_mom, sizeof(double) * per * c.count,
+                                            hipMemcpyDeviceToDevice, st));
             continue;
         }
         prof_begin(plan, 2, st);
-        if (plan->mode == 1) {
+        if (split) {
+            launch_contract_split(problem, plan->N, plan->d_desc, c.e0, c.count, ctx->d_tab32,
+                                  reinterpret_cast<const float *>(plan->d_mom), out, status,
+                                  plan->terms.stiff_scale, plan->terms.mass_scale, st);
+        } else if (plan->mode == 1) {
             launch_contract_persistent(problem, plan->d_desc, plan->d_items + c.item0, c.nitem, plan->d_counter,
                                        plan->num_cu * plan->wpc, ctx->d_tab, plan->d_mom, out, status,
                                        plan->terms.stiff_scale, plan->terms.mass_scale, st);

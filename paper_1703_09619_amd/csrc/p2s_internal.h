@@ -113,6 +113,22 @@ constexpr int TAB_SIZE = TAB_TAILW + (MAXQ + 1) * TAILW_STRIDE_Q;
 // the tensor the axis was examined on at 12+axis.
 constexpr int TAIL_REC = 16;
 
+// FP32 two-term split tables of the split-precision path (floats):
+// x = hi + lo with hi = fl32(x), lo = fl32(x - hi), for the linearization
+// coefficients lin[t][m1][m2][k] (k < KPAD) and the moment weights
+// legw[Q][k][a] (k, a < 16).
+constexpr int T32_LIN = NTYPE * MAXN * MAXN * KPAD;
+constexpr int T32_LEGW_Q = 16 * 16;
+constexpr int T32_LEGW = (MAXQ + 1) * T32_LEGW_Q;
+constexpr int T32_LIN_H = 0;
+constexpr int T32_LIN_L = T32_LIN_H + T32_LIN;
+constexpr int T32_LEGW_H = T32_LIN_L + T32_LIN;
+constexpr int T32_LEGW_L = T32_LEGW_H + T32_LEGW;
+constexpr int T32_SIZE = T32_LEGW_L + T32_LEGW;
+// the split path samples at most this many points per axis (one MFMA
+// K-block of 16)
+constexpr int SPLIT_MAXQ = 16;
+
 // Mirrors of the public enums and status bits (include/p2s.h).
 enum MatKind : int { MAT_SINCOSEXP = 0, MAT_ROTDIAG = 1, MAT_PLANEWAVE = 2, ALPHA_SAMPLED = 3 };
 constexpr uint32_t P2S_STATUS_DETJ_BIT = 1u;
