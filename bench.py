@@ -49,6 +49,33 @@ def contract_bytes_per_element(problem: int, N: int, moment_bytes: int = 8) -> i
     return 8 * nd * nd + moment_bytes * F * K ** 3
 
 
+TRAFFIC_PROFILES = {("vector_n6", "fp64"): "profiles/k_contract_vector_n6.md"}
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per contraction stage from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-probe factors), or
+    None when there is none or the contraction sources changed since."""
+    import hashlib
+    name = TRAFFIC_PROFILES.get((workload, precision))
+    if name is None or not os.path.exists(os.path.join(ROOT, name)):
+        return None
+    fields = {}
+    for line in open(os.path.join(ROOT, name)):
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_step", "sources_sha256", "sources"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for f in fields["sources"].split():
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != fields["sources_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_step"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def cpu_threads() -> int:
     try:
         n = len(os.sched_getaffinity(0))
@@ -124,19 +151,31 @@ def main():
     value = w.E / (ms_per_step * 1e-3)
     st = status.cpu().numpy()
 
-    # dominant kernel: the contraction (HIP events on the launch stream)
-    c_ms, c_launches = stages["contraction"]
+    # dominant kernel: the contraction stage (HIP events on the launch stream
+    # around the stage's launches: one kernel per row component, or one
+    # persistent kernel, or one kernel per block in the split form)
+    c_ms, c_segments = stages["contraction"]
     if w.problem == 0 and len(set(w.orders.tolist())) > 1:
         alg_bytes = sum(contract_bytes_per_element(0, int(n)) for n in w.orders)
     else:
         alg_bytes = w.E * contract_bytes_per_element(w.problem, int(w.orders[0]), 4 if split else 8)
-    alg_bytes_per_launch = alg_bytes * args.steps / max(c_launches, 1)
-    avg_launch_s = c_ms * 1e-3 / max(c_launches, 1)
-    achieved = alg_bytes_per_launch / avg_launch_s / 1e9
+    stage_ms = c_ms / args.steps
+    achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
+    n_uniform = len(set(w.orders.tolist())) == 1
+    if split:
+        kname, per_chunk = "k_contract_split<%d,I,J> (blocks J >= I)" % w.problem, 6 if w.problem else 1
+    elif not n_uniform:
+        kname, per_chunk = "k_contract_persistent_scalar", 1
+    else:
+        kname = "k_contract<%d,%d,I> (row components I)" % (w.problem, int(w.orders[0]))
+        per_chunk = 3 if w.problem else 1
+    traffic = measured_traffic(args.workload, args.precision)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_contract_split" if split else "k_contract", "avg_launch_ms": round(c_ms / max(c_launches, 1), 4),
-                "launches_per_step": c_launches // args.steps}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "kernel": kname, "unit_of_work": "one contraction stage over the batch",
+                "algorithmic_bytes": alg_bytes, "stage_ms": round(stage_ms, 4),
+                "launches_per_step": (c_segments // args.steps) * per_chunk}
 
     if learned is not None:
         # the same plan without the network (full rule on every axis)
