@@ -231,26 +231,27 @@ int p2s_mlp_predict(p2s_ctx ctx, int64_t B, const float *x, float p_cover, int32
  * runs the network, chooses per axis the smallest K whose predicted
  * cumulative probability reaches p_cover (K >= k_direct: the full rule at
  * once; k_direct > P2S_KMAX disables that), samples the coupling factor with
- * the chosen rules and checks the tail.  Along each axis the moment stage takes, on every line it
- * contracts (samples for w, w-moments for v, (v,w)-moments for u), the
- * discrete Legendre coefficients of the four highest degrees the rule
- * resolves; their decay extrapolated to the first degree the moments of
- * eq. (4) can alias, relative to the largest value of that tensor, is the
- * axis statistic.  Its maximum over the axes sampled below the full rule is
- * the element's tail value; above theta the element is sampled again with
- * the full rule (status P2S_STATUS_FALLBACK).  Axes already at the full
- * rule take no statistic.  Allocates its workspace here;
- * enable = 0 restores the plan's own rules. */
+ * the chosen rules and checks the tail.  Along each axis the moment stage
+ * takes, on every line it contracts (samples for u, u-moments for v,
+ * (u,v)-moments for w), the discrete Legendre coefficients of the four
+ * highest degrees the rule resolves; their decay extrapolated to the first
+ * degree the moments of eq. (4) can alias, relative to the largest value of
+ * that tensor, is the axis statistic.  Its maximum over the axes sampled
+ * below the full rule is the element's tail value; above theta the element
+ * is sampled again with the full rule (status P2S_STATUS_FALLBACK).  Axes
+ * already at the full rule take no statistic.  Orders up to 6 (P2S_EORDER
+ * otherwise).  Allocates its workspace here; enable = 0 restores the plan's
+ * own rules. */
 int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, int k_direct, double theta);
 /* Tail records of the moment stage at the plan's own rules (coupling and
  * moments only; no contraction): records [device][E][F][16], per field
  * env[axis][j] at axis*4+j, j = 0..3 for the degrees Q-1..Q-4 of that axis
- * (axis 0 = u on the (v,w)-moments, 1 = v on the w-moments, 2 = w on the
- * samples), and the largest magnitude of the tensor each axis was examined
+ * (axis 0 = u on the samples, 1 = v on the u-moments, 2 = w on the
+ * (u,v)-moments), and the largest magnitude of the tensor each axis was examined
  * on at 12+axis; entry 15 is zero, and so is every entry of an axis sampled
  * with P2S_KMAX points or more.  The statistic of p2s_plan_set_learned
- * is computed from these.  Product-to-sum plans; allocates its workspace on
- * first use. */
+ * is computed from these.  Product-to-sum plans of orders up to 6;
+ * allocates its workspace on first use. */
 int p2s_plan_tail_records(p2s_plan plan, const double *nodes, const double *material, double *records,
                           void *stream);
 /* Rules used by the last execution: quad [host][E][3]. */

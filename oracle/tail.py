@@ -14,10 +14,10 @@ function has Legendre content of degree >= 2Q-k along it.
 Per field, the record holds for each axis the envelope (largest magnitude
 over lines) of c_{Q-1}, ..., c_{Q-4} and the largest magnitude of the tensor
 whose lines were taken:
-    axis w: lines of the samples alpha[a][b][.];
-    axis v: lines of the w-moments P1[a][.][q] = sum_c W_w[q][c] alpha[a][b][c];
-    axis u: lines of the (v,w)-moments P2[.][l][q] = sum_b W_v[l][b] P1[a][b][q];
-with W[k][a] = w_a L_k(x_a), k, l, q < K_m.  An axis sampled with the full
+    axis u: lines of the samples alpha[.][b][c];
+    axis v: lines of the u-moments P1[k][.][c] = sum_a W_u[k][a] alpha[a][b][c];
+    axis w: lines of the (u,v)-moments P2[k][l][.] = sum_b W_v[l][b] P1[k][b][c];
+with W[k][a] = w_a L_k(x_a), k, l < K_m.  An axis sampled with the full
 rule (Q >= qfull) records zeros.  The element's tail value combines, over
 the fields, the envelopes A_j and scale S of each reduced axis as
     r2 = min(1, max(A_1/A_3, A_2/A_4)),
@@ -69,25 +69,24 @@ def records(alpha, Qu, Qv, Qw, N, qfull=24):
     out = np.zeros((F, REC))
     xu, wu = _rule(Qu)
     xv, wv = _rule(Qv)
-    xw, ww = _rule(Qw)
+    Wu = _legendre_rows(xu, Km) * wu
     Wv = _legendre_rows(xv, Km) * wv
-    Ww = _legendre_rows(xw, Km) * ww
     for f in range(F):
         a = A[f]
-        P1 = np.einsum("qc,abc->abq", Ww, a)      # [Qu][Qv][Km]
-        P2 = np.einsum("lb,abq->alq", Wv, P1)     # [Qu][Km][Km]
-        if Qw < qfull:
-            c = np.einsum("jc,abc->jab", _tail_rows(Qw), a)
-            out[f, 8:12] = np.abs(c).reshape(4, -1).max(1)
-            out[f, 14] = np.abs(a).max()
+        P1 = np.einsum("ka,abc->kbc", Wu, a)      # [Km][Qv][Qw]
+        P2 = np.einsum("lb,kbc->klc", Wv, P1)     # [Km][Km][Qw]
+        if Qu < qfull:
+            c = np.einsum("ja,abc->jbc", _tail_rows(Qu), a)
+            out[f, 0:4] = np.abs(c).reshape(4, -1).max(1)
+            out[f, 12] = np.abs(a).max()
         if Qv < qfull:
-            c = np.einsum("jb,abq->jaq", _tail_rows(Qv), P1)
+            c = np.einsum("jb,kbc->jkc", _tail_rows(Qv), P1)
             out[f, 4:8] = np.abs(c).reshape(4, -1).max(1)
             out[f, 13] = np.abs(P1).max()
-        if Qu < qfull:
-            c = np.einsum("ja,alq->jlq", _tail_rows(Qu), P2)
-            out[f, 0:4] = np.abs(c).reshape(4, -1).max(1)
-            out[f, 12] = np.abs(P2).max()
+        if Qw < qfull:
+            c = np.einsum("jc,klc->jkl", _tail_rows(Qw), P2)
+            out[f, 8:12] = np.abs(c).reshape(4, -1).max(1)
+            out[f, 14] = np.abs(P2).max()
     return out
 
 

@@ -51,7 +51,7 @@ struct p2s_plan_s {
     int64_t E = 0;
     bool uniform = true;
     int N = 0, Qu = 0, Qv = 0, Qw = 0;
-    int maxN = 0, maxQu = 0, maxQuv = 0;
+    int maxN = 0, maxQw = 0, maxQvw = 0;  // largest order and moment-stage LDS shape
     int mat_stride = 0;
     std::vector<int32_t> orders, quad;
     std::vector<int64_t> offsets;
@@ -315,8 +315,8 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
                             (long long)e, quad[3 * e + a], a, P2S_MAX_Q);
             }
         plan->maxN = std::max(plan->maxN, N);
-        plan->maxQu = std::max(plan->maxQu, (int)quad[3 * e]);
-        plan->maxQuv = std::max(plan->maxQuv, (int)(quad[3 * e] * quad[3 * e + 1]));
+        plan->maxQw = std::max(plan->maxQw, (int)quad[3 * e + 2]);
+        plan->maxQvw = std::max(plan->maxQvw, (int)(quad[3 * e + 1] * quad[3 * e + 2]));
         if (e > 0 && (N != orders[0] || quad[3 * e] != quad[0] || quad[3 * e + 1] != quad[1] ||
                       quad[3 * e + 2] != quad[2]))
             plan->uniform = false;
@@ -342,7 +342,7 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
         return fail(ctx, P2S_EQUAD, "plan: split-FP32 precision takes one order and one rule of at most %d points "
                                     "per axis for all elements", SPLIT_MAXQ);
     }
-    if (E > 0 && moments_smem_bytes(plan->maxN, plan->maxQu, plan->maxQuv) > LDS_LIMIT) {
+    if (E > 0 && moments_smem_bytes(plan->maxN, plan->maxQw, plan->maxQvw) > LDS_LIMIT) {
         delete plan;
         return fail(ctx, P2S_EQUAD, "plan: rule too large for the moment stage at order %d", plan->maxN);
     }
@@ -497,7 +497,7 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
             launch_moments_split(problem, plan->d_desc, c.e0, c.count, plan->d_alpha, ctx->d_tab32,
                                  reinterpret_cast<float *>(plan->d_mom), st);
         else
-            launch_moments(problem, plan->maxN, plan->maxQu, plan->maxQuv, plan->d_desc, c.e0, c.count,
+            launch_moments(problem, plan->maxN, plan->maxQw, plan->maxQvw, plan->d_desc, c.e0, c.count,
                            plan->d_alpha, ctx->d_tab, plan->d_mom, nullptr,
                            (learned || stop == STOP_TAILREC) ? plan->d_tailst : nullptr, st);
         prof_end(plan, 1, st);
@@ -509,7 +509,7 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
                                plan->d_redo, status, plan->d_tau, st);
             launch_coupling(problem, plan->d_desc, c.e0, c.count, nodes, material, plan->terms.material,
                             plan->mat_stride, ctx->d_tab, plan->d_alpha, status, plan->d_redo, st);
-            launch_moments(problem, plan->maxN, plan->maxQu, plan->maxQuv, plan->d_desc, c.e0, c.count,
+            launch_moments(problem, plan->maxN, plan->maxQw, plan->maxQvw, plan->d_desc, c.e0, c.count,
                            plan->d_alpha, ctx->d_tab, plan->d_mom, plan->d_redo, nullptr, st);
             prof_end(plan, 3, st);
         }
@@ -605,6 +605,7 @@ int p2s_plan_tail_records(p2s_plan plan, const double *nodes, const double *mate
     if (!plan) return P2S_EINVAL;
     p2s_ctx ctx = plan->ctx;
     if (plan->terms.method != P2S_METHOD_P2S) return fail(ctx, P2S_EINVAL, "tail records need the product-to-sum method");
+    if (plan->maxN > TAIL_MAXN) return fail(ctx, P2S_EORDER, "tail records: orders up to %d", TAIL_MAXN);
     if (plan->E > 0 && !plan->d_tailst) {
         HIP_TRY(ctx, hipSetDevice(ctx->device));
         const int64_t n = plan->E * num_fields(plan->terms.problem) * TAIL_REC;
@@ -1005,6 +1006,7 @@ int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, int k_direct,
         plan->Qu != MLP_KMAX || plan->Qv != MLP_KMAX || plan->Qw != MLP_KMAX)
         return fail(ctx, P2S_EINVAL, "learned order: needs a uniform product-to-sum plan created with %d points "
                                      "per axis", MLP_KMAX);
+    if (plan->N > TAIL_MAXN) return fail(ctx, P2S_EORDER, "learned order: orders up to %d", TAIL_MAXN);
     if (!(p_cover > 0.f && p_cover <= 1.f) || !(theta > 0.0) || k_direct < MLP_KMIN)
         return fail(ctx, P2S_EINVAL, "learned order: bad p_cover / k_direct / theta");
     if (!plan->d_lx && plan->E > 0) {

@@ -104,7 +104,9 @@ struct CS {
     static constexpr int A_DOUBLES = N * K * KS;                    // stage-A result per group
     static constexpr int C_DOUBLES = NN_I * max_over_j(2) * KS;      // stage-B coefficients per group
     static constexpr int GROUP_DOUBLES = A_DOUBLES + C_DOUBLES;
-    static constexpr int G = cmax(1, cmin(MAXG, 7936 / GROUP_DOUBLES));  // groups per LDS batch (~62 KiB)
+    // groups per LDS batch: ~52 KiB up to N = 6 (three workgroups per CU,
+    // with at most 168 VGPRs, see k_contract), ~62 KiB above
+    static constexpr int G = cmax(1, cmin(MAXG, (N <= 6 ? 6656 : 7936) / GROUP_DOUBLES));
     static constexpr int TILE_MIN = (max_over_j(3) + 2) * NP_I;     // one n1 of the store tile
     static constexpr int BUF = cmax(G * GROUP_DOUBLES, TILE_MIN);
     static constexpr int SA = ((K * K + 63) / 64) * 64;              // stage-A workers per group
@@ -300,7 +302,9 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
         // columns (m2, n2, p2), m2 >= m2lo; n1 goes in chunks that fit
         {
             const int W = nm * NN_J * NP_J;     // tile width
-            const int WS = W + 2 - (W & 1);     // padded row stride (even)
+            // odd row stride: the transposed (mirror) reads below step two rows
+            // per lane, which an odd stride spreads over distinct LDS banks
+            const int WS = W | 1;
             int cn = S::BUF / (WS * NP_I);
             cn = cn < 1 ? 1 : cn;
             const int colj = comp_offset(PROB, N, J) + m2lo * NN_J * NP_J;
@@ -327,8 +331,9 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                     const int hw = W / 2;
                     for (int x = tid; x < nr * hw; x += nthreads) {
                         const int r = x / hw, c = 2 * (x - r * hw);
+                        // two 8-byte LDS reads (rows are only 8-byte aligned)
                         *reinterpret_cast<double2 *>(drow + (int64_t)r * NDOF + c) =
-                            *reinterpret_cast<const double2 *>(smem + r * WS + c);
+                            make_double2(smem[r * WS + c], smem[r * WS + c + 1]);
                     }
                 } else {
                     for (int x = tid; x < nr * W; x += nthreads) {
@@ -363,7 +368,7 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
 }
 
 template <int PROB, int N, int I>
-__global__ __launch_bounds__((CS<PROB, N, I>::THREADS)) void k_contract(
+__global__ __launch_bounds__((CS<PROB, N, I>::THREADS), (N <= 6 ? 3 : 2)) void k_contract(
     const ElemDesc *__restrict__ desc, const int32_t *__restrict__ elist, int64_t e0, int64_t nitems,
     int64_t padded, const double *__restrict__ tab, const double *__restrict__ mom,
     double *__restrict__ out, uint32_t *__restrict__ status, double sK, double sM)

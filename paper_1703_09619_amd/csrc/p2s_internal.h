@@ -112,6 +112,9 @@ constexpr int TAB_SIZE = TAB_TAILW + (MAXQ + 1) * TAILW_STRIDE_Q;
 // mode: env[axis][j] at axis*4+j (axis 0 = u, 1 = v, 2 = w), the scale of
 // the tensor the axis was examined on at 12+axis.
 constexpr int TAIL_REC = 16;
+// the moment stage carries the four tail rows beside the 2N-1 moment rows
+// in one 16-row matrix-core tile: orders up to 6
+constexpr int TAIL_MAXN = 6;
 
 // FP32 two-term split tables of the split-precision path (floats):
 // x = hi + lo with hi = fl32(x), lo = fl32(x - hi), for the linearization

@@ -11,14 +11,14 @@ namespace p2s {
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
 int prepare_kernels();
-size_t moments_smem_bytes(int maxN, int maxQu, int maxQuv);
+size_t moments_smem_bytes(int maxN, int maxQw, int maxQvw);
 
 // `only` (may be null): elements with only[e] == 0 are skipped; with it the
 // coupling kernel ORs its status bits instead of overwriting them.
 void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t count,
                      const double *nodes, const double *mat, int kind, int mat_stride,
                      const double *tab, double *alpha, uint32_t *status, const int32_t *only, hipStream_t st);
-void launch_moments(int problem, int maxN, int maxQu, int maxQuv, const ElemDesc *desc, int64_t e0,
+void launch_moments(int problem, int maxN, int maxQw, int maxQvw, const ElemDesc *desc, int64_t e0,
                     int64_t count, const double *alpha, const double *tab, double *mom, const int32_t *only,
                     double *tailst, hipStream_t st);
 int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0,

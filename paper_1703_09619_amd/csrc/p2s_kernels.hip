@@ -29,10 +29,11 @@ __device__ __forceinline__ void lagrange3(double t, double l[3], double d[3])
     d[2] = t + 0.5;
 }
 
-// eps(x) as a symmetric tensor (e00 e11 e22 e01 e02 e12).
-__device__ __forceinline__ void permittivity(int kind, const double *p, const double x[3], double e[6])
+// eps(x) as a symmetric tensor (e00 e11 e22 e01 e02 e12) for material KIND.
+template <int KIND>
+__device__ __forceinline__ void permittivity(const double *p, const double x[3], double e[6])
 {
-    if (kind == MAT_ROTDIAG) {
+    if constexpr (KIND == MAT_ROTDIAG) {
         const double kx = p[9] * x[0] + p[10] * x[1] + p[11] * x[2];
         const double c3 = 2.0943951023931954923;  // 2 pi / 3
         double d[3];
@@ -48,49 +49,24 @@ __device__ __forceinline__ void permittivity(int kind, const double *p, const do
             for (int a = 0; a < 3; ++a) v = fma(p[3 * a + rr[s]] * d[a], p[3 * a + cc[s]], v);
             e[s] = v;
         }
-        return;
+    } else {
+        double v;
+        if constexpr (KIND == MAT_PLANEWAVE)
+            v = 1.0 + 0.8 * sin(p[0] * x[0] + p[1] * x[1] + p[2] * x[2] + p[3]);
+        else
+            v = 1.0 + 0.5 * sin(p[0] * x[0]) * cos(p[0] * x[1]) * exp(-x[2]);
+        e[0] = e[1] = e[2] = v;
+        e[3] = e[4] = e[5] = 0.0;
     }
-    double v;
-    if (kind == MAT_PLANEWAVE)
-        v = 1.0 + 0.8 * sin(p[0] * x[0] + p[1] * x[1] + p[2] * x[2] + p[3]);
-    else
-        v = 1.0 + 0.5 * sin(p[0] * x[0]) * cos(p[0] * x[1]) * exp(-x[2]);
-    e[0] = e[1] = e[2] = v;
-    e[3] = e[4] = e[5] = 0.0;
 }
 
-// Coupling fields at reference point (u,v,w) of an element with nodes X.
-// Returns det J; writes F fields (packed order of P2S_ALPHA_SAMPLED).
-template <int PROB>
-__device__ __forceinline__ double coupling_point(const double *X, int kind, const double *mp,
-                                                 double u, double v, double w, double *f)
+// Coupling fields at one point from the map value x and Jacobian
+// J[r][c] = dx_r/du_c.  Returns det J; writes F fields (packed order of
+// P2S_ALPHA_SAMPLED).
+template <int PROB, int KIND>
+__device__ __forceinline__ double coupling_fields(const double x[3], const double J[3][3], const double *mp,
+                                                  double *f)
 {
-    double lu[3], du[3], lv[3], dv[3], lw[3], dw[3];
-    lagrange3(u, lu, du);
-    lagrange3(v, lv, dv);
-    lagrange3(w, lw, dw);
-    double x[3] = {0, 0, 0}, J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            // contract the u-direction first
-            double s[3], su[3];
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const double *Xr = X + 3 * (3 * j + 9 * k) + r;
-                s[r] = lu[0] * Xr[0] + lu[1] * Xr[3] + lu[2] * Xr[6];
-                su[r] = du[0] * Xr[0] + du[1] * Xr[3] + du[2] * Xr[6];
-            }
-            const double a0 = lv[j] * lw[k], a1 = dv[j] * lw[k], a2 = lv[j] * dw[k];
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                x[r] = fma(a0, s[r], x[r]);
-                J[r][0] = fma(a0, su[r], J[r][0]);
-                J[r][1] = fma(a1, s[r], J[r][1]);
-                J[r][2] = fma(a2, s[r], J[r][2]);
-            }
-        }
     // adjugate: adj[a][b] = cofactor[b][a]
     double adj[3][3];
     adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
@@ -105,7 +81,7 @@ __device__ __forceinline__ double coupling_point(const double *X, int kind, cons
     const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
     const double rdet = 1.0 / det;
     double e[6];
-    permittivity(kind, mp, x, e);
+    permittivity<KIND>(mp, x, e);
     const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
     if (PROB == 0) {
         // eps det J J^-1 J^-T = eps adj adj^T / det
@@ -138,11 +114,16 @@ __device__ __forceinline__ double coupling_point(const double *X, int kind, cons
 }
 
 // One workgroup per element: coupling fields at all Gauss points,
-// alpha[alpha_off + f*P + (a*Qv+b)*Qw + c], unweighted.
-template <int PROB>
+// alpha[alpha_off + f*P + (a*Qv+b)*Qw + c], unweighted.  The triquadratic
+// map is sum-factorized: a thread takes a line of points along u (fixed
+// v_b, w_c), contracts the node array over the (v,w) Lagrange factors once,
+//   Y[i] = sum_jk lv_j lw_k X_ijk,  Yv[i] = sum_jk dv_j lw_k X_ijk,
+//   Yw[i] = sum_jk lv_j dw_k X_ijk,
+// and then evaluates x and J at each point of the line from 3 terms each.
+template <int PROB, int KIND>
 __global__ __launch_bounds__(256) void k_coupling(const ElemDesc *__restrict__ desc, int64_t e0,
                                                   const double *__restrict__ nodes,
-                                                  const double *__restrict__ mat, int kind,
+                                                  const double *__restrict__ mat,
                                                   int mat_stride, const double *__restrict__ tab,
                                                   double *__restrict__ alpha,
                                                   uint32_t *__restrict__ status,
@@ -153,11 +134,11 @@ __global__ __launch_bounds__(256) void k_coupling(const ElemDesc *__restrict__ d
     if (only && !only[e]) return;
     const ElemDesc d = desc[e];
     const int Qu = d.Qu, Qv = d.Qv, Qw = d.Qw;
-    const int P = Qu * Qv * Qw;
+    const int P = Qu * Qv * Qw, L = Qv * Qw;
     double *dst = alpha + d.alpha_off;
     __shared__ double X[81];
     __shared__ double mp[16];
-    if (kind == ALPHA_SAMPLED) {
+    if constexpr (KIND == ALPHA_SAMPLED) {
         const double *src = mat + e * (int64_t)(F * P);
         for (int i = threadIdx.x; i < F * P; i += blockDim.x) dst[i] = src[i];
         if (threadIdx.x == 0 && !only) status[e] = 0u;
@@ -170,15 +151,56 @@ __global__ __launch_bounds__(256) void k_coupling(const ElemDesc *__restrict__ d
     const double *gv = tab + TAB_GX + Qv * MAXQ;
     const double *gw = tab + TAB_GX + Qw * MAXQ;
     int bad = 0;
-    for (int pt = threadIdx.x; pt < P; pt += blockDim.x) {
-        const int c = pt % Qw;
-        const int b = (pt / Qw) % Qv;
-        const int a = pt / (Qw * Qv);
-        double f[F];
-        const double det = coupling_point<PROB>(X, kind, mp, gu[a], gv[b], gw[c], f);
-        bad |= !(det > 0.0);
+    for (int ln = threadIdx.x; ln < L; ln += blockDim.x) {
+        const int b = ln / Qw, c = ln - (ln / Qw) * Qw;
+        double lv[3], dv[3], lw[3], dw[3];
+        lagrange3(gv[b], lv, dv);
+        lagrange3(gw[c], lw, dw);
+        double Y[3][3], Yv[3][3], Yw[3][3];  // [i][r]
+        // the node array is read from LDS here, line by line (held in
+        // registers across the line loop it would take 162 VGPRs): an
+        // opaque zero offset keeps the reads inside the loop
+        int xo = 0;
+        asm volatile("" : "+v"(xo));
+        const double *Xv = X + xo;
 #pragma unroll
-        for (int s = 0; s < F; ++s) dst[(int64_t)s * P + pt] = f[s];
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                double y = 0.0, yv = 0.0, yw = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    // t_j = X_ijk for j = 0..2
+                    const double t0 = Xv[3 * (i + 9 * k) + r], t1 = Xv[3 * (i + 3 + 9 * k) + r],
+                                 t2 = Xv[3 * (i + 6 + 9 * k) + r];
+                    const double sl = lv[0] * t0 + lv[1] * t1 + lv[2] * t2;
+                    const double sd = dv[0] * t0 + dv[1] * t1 + dv[2] * t2;
+                    y = fma(lw[k], sl, y);
+                    yv = fma(lw[k], sd, yv);
+                    yw = fma(dw[k], sl, yw);
+                }
+                Y[i][r] = y;
+                Yv[i][r] = yv;
+                Yw[i][r] = yw;
+            }
+        for (int a = 0; a < Qu; ++a) {
+            double lu[3], du[3];
+            lagrange3(gu[a], lu, du);
+            double x[3], J[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                x[r] = lu[0] * Y[0][r] + lu[1] * Y[1][r] + lu[2] * Y[2][r];
+                J[r][0] = du[0] * Y[0][r] + du[1] * Y[1][r] + du[2] * Y[2][r];
+                J[r][1] = lu[0] * Yv[0][r] + lu[1] * Yv[1][r] + lu[2] * Yv[2][r];
+                J[r][2] = lu[0] * Yw[0][r] + lu[1] * Yw[1][r] + lu[2] * Yw[2][r];
+            }
+            double f[F];
+            const double det = coupling_fields<PROB, KIND>(x, J, mp, f);
+            bad |= !(det > 0.0);
+            const int64_t pt = (int64_t)a * L + ln;
+#pragma unroll
+            for (int s = 0; s < F; ++s) dst[(int64_t)s * P + pt] = f[s];
+        }
     }
     bad = __syncthreads_or(bad);
     if (threadIdx.x == 0) {
@@ -191,16 +213,33 @@ __global__ __launch_bounds__(256) void k_coupling(const ElemDesc *__restrict__ d
 
 // ---------------------------------------------------------------------------
 // Moments, eq. (4): I[k][l][q] = sum_{a,b,c} Wu[k][a] Wv[l][b] Ww[q][c] alpha[a][b][c]
-// with W[k][a] = w_a L_k(x_a), as three passes (contract w, then v, then u).
-// One workgroup per (element, field); the sizes are runtime, the degree
-// count K = 2N-1 selects a register-blocked instantiation.
+// with W[k][a] = w_a L_k(x_a), as three dense GEMM passes on the FP64 matrix
+// cores (v_mfma_f64_16x16x4f64), contracting u, then v, then w:
+//   pass 1  P1[k][(b,c)] = sum_a Wu[k][a] alpha[a][(b,c)]   (operand B read
+//           straight from HBM: 16 consecutive samples per row, coalesced)
+//   pass 2  P2[k][l][c]  = sum_b Wv[l][b] P1[k][b][c]       (N = (k,c))
+//   pass 3  I[k][l][q]   = sum_c Ww[q][c] P2[k][l][c]       (N = (k,l))
+// Each pass is M = 16 rows (K = 2N-1 <= 15 moment degrees) by N columns in
+// tiles of 16, with the summed index in steps of 4.  One workgroup (4 waves)
+// per (element, field); the waves take the N tiles in turn.
 //
-// TAIL (learned order): each pass whose axis is sampled below the full
-// rule MLP_KMAX also takes, on every line it contracts, the discrete
-// Legendre coefficients of the four highest degrees its rule resolves (w on
-// the samples, v on the w-moments, u on the (v,w)-moments), keeps their
-// largest magnitudes and the largest magnitude of the tensor it reads, and
-// writes them as the (element, field) tail record (zeros for full axes).
+// TAIL (learned order, K + 4 <= 16): rows K..K+3 of a pass whose axis is
+// sampled below the full rule MLP_KMAX hold the discrete Legendre
+// coefficients of the four highest degrees its rule resolves, on every line
+// it contracts (u on the samples, v on the u-moments, w on the (u,v)-
+// moments); the pass keeps their largest magnitudes and the largest
+// magnitude of the tensor it reads, and the workgroup writes them as the
+// (element, field) tail record (zeros for full axes).
+//
+// FP64 MFMA 16x16x4 lane layout (wave64): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; result register i of lane l is D[4i + l/16][l%16].
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 __device__ __forceinline__ double wave_max(double v)
 {
@@ -209,102 +248,133 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-template <int K, bool TAIL>
+// Operand-A value of row m for a pass over an axis with Q points: moment
+// weights for m < K, tail weights for K <= m < K+4 when `tail`, else 0;
+// column a (zero beyond Q in both tables).
+__device__ __forceinline__ double pass_weight(const double *__restrict__ tab, int Q, int K, bool tail, int m, int a)
+{
+    if (a >= MAXQ) return 0.0;
+    if (m < K) return tab[TAB_LEGW + Q * LEGW_STRIDE_Q + m * MAXQ + a];
+    if (tail && m < K + 4) return tab[TAB_TAILW + Q * TAILW_STRIDE_Q + (m - K) * MAXQ + a];
+    return 0.0;
+}
+
+template <bool TAIL>
 __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const double *__restrict__ alpha,
                              const double *__restrict__ tab, double *__restrict__ mom, double *sm,
                              int p2off, double *__restrict__ tailst)
 {
-    const int Qu = d.Qu, Qv = d.Qv, Qw = d.Qw;
-    const int P = Qu * Qv * Qw;
+    const int Qu = d.Qu, Qv = d.Qv, Qw = d.Qw, K = 2 * d.N - 1;
+    const int L = Qv * Qw, P = Qu * L;
+    const int QWS = Qw | 1;  // odd row stride of P2
     const double *A = alpha + d.alpha_off + (int64_t)f * P;
-    const double *Wu = tab + TAB_LEGW + Qu * LEGW_STRIDE_Q;
-    const double *Wv = tab + TAB_LEGW + Qv * LEGW_STRIDE_Q;
-    const double *Ww = tab + TAB_LEGW + Qw * LEGW_STRIDE_Q;
-    const double *Tu = tab + TAB_TAILW + Qu * TAILW_STRIDE_Q;
-    const double *Tv = tab + TAB_TAILW + Qv * TAILW_STRIDE_Q;
-    const double *Tw = tab + TAB_TAILW + Qw * TAILW_STRIDE_Q;
-    constexpr int KS = K + 1;  // LDS row stride
-    double *P1 = sm;          // [Qu*Qv][KS]   (q)
-    double *P2 = sm + p2off;  // [Qu][K][KS]   (l, q)
-    const int tid = threadIdx.x, nt = blockDim.x;
+    double *P1 = sm;          // [K][Qv*Qw]    (k; b, c)
+    double *P2 = sm + p2off;  // [K][K][QWS]   (k, l; c)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const int r16 = lane & 15, k4 = lane >> 4;
     double rec[TAIL_REC];
 #pragma unroll
     for (int i = 0; i < TAIL_REC; ++i) rec[i] = 0.0;
     // workgroup-uniform: which axes take the tail statistic
     const bool tu = TAIL && Qu < MLP_KMAX, tv = TAIL && Qv < MLP_KMAX, tw = TAIL && Qw < MLP_KMAX;
-    // pass 1: contract w
-    for (int ab = tid; ab < Qu * Qv; ab += nt) {
-        double acc[K], tl[4] = {0.0, 0.0, 0.0, 0.0};
+    double wa[MAXQ / 4];  // operand A of the current pass, one value per step of 4
+
+    // pass 1: contract u; columns (b,c).  A wave takes TG consecutive column
+    // tiles at a time and issues all their sample loads before the matrix
+    // operations, so that many HBM loads are in flight per lane.
+    constexpr int TG = 4;
+    const int su = (Qu + 3) >> 2;
 #pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] = 0.0;
-        const double *Ar = A + (int64_t)ab * Qw;
-        for (int c = 0; c < Qw; ++c) {
-            const double x = Ar[c];
+    for (int ks = 0; ks < MAXQ / 4; ++ks) wa[ks] = ks < su ? pass_weight(tab, Qu, K, tu, r16, 4 * ks + k4) : 0.0;
+    for (int nt0 = wave * TG; nt0 * 16 < L; nt0 += nwave * TG) {
+        double xs[TG][MAXQ / 4];
 #pragma unroll
-            for (int q = 0; q < K; ++q) acc[q] = fma(Ww[q * MAXQ + c], x, acc[q]);
-            if (tw) {
+        for (int t = 0; t < TG; ++t) {
+            const int col = (nt0 + t) * 16 + r16;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) tl[j] = fma(Tw[j * MAXQ + c], x, tl[j]);
-                rec[14] = fmax(rec[14], fabs(x));
+            for (int ks = 0; ks < MAXQ / 4; ++ks) {
+                const int a = 4 * ks + k4;
+                xs[t][ks] = (ks < su && a < Qu && col < L) ? A[(int64_t)a * L + col] : 0.0;
             }
         }
-        if (tw)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) rec[8 + j] = fmax(rec[8 + j], fabs(tl[j]));
+        for (int t = 0; t < TG; ++t) {
+            const int col = (nt0 + t) * 16 + r16;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < K; ++q) P1[ab * KS + q] = acc[q];
-    }
-    __syncthreads();
-    // pass 2: contract v
-    for (int aq = tid; aq < Qu * K; aq += nt) {
-        const int a = aq / K, q = aq - (aq / K) * K;
-        double acc[K], tl[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int ks = 0; ks < MAXQ / 4; ++ks) {
+                if (ks < su) {
+                    if (tu) rec[12] = fmax(rec[12], fabs(xs[t][ks]));
+                    acc = mfma64(wa[ks], xs[t][ks], acc);
+                }
+            }
 #pragma unroll
-        for (int l = 0; l < K; ++l) acc[l] = 0.0;
-        for (int b = 0; b < Qv; ++b) {
-            const double x = P1[(a * Qv + b) * KS + q];
-#pragma unroll
-            for (int l = 0; l < K; ++l) acc[l] = fma(Wv[l * MAXQ + b], x, acc[l]);
-            if (tv) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) tl[j] = fma(Tv[j * MAXQ + b], x, tl[j]);
-                rec[13] = fmax(rec[13], fabs(x));
+            for (int i = 0; i < 4; ++i) {
+                const int m = 4 * i + k4;
+                if (col < L) {
+                    if (m < K) P1[m * L + col] = acc[i];
+                    else if (tu && m < K + 4) rec[m - K] = fmax(rec[m - K], fabs(acc[i]));
+                }
             }
         }
-        if (tv)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) rec[4 + j] = fmax(rec[4 + j], fabs(tl[j]));
-#pragma unroll
-        for (int l = 0; l < K; ++l) P2[(a * K + l) * KS + q] = acc[l];
     }
     __syncthreads();
-    // pass 3: contract u
+    // pass 2: contract v; columns n = (k, c)
+    const int sv = (Qv + 3) >> 2, n2 = K * Qw;
+#pragma unroll
+    for (int ks = 0; ks < MAXQ / 4; ++ks) wa[ks] = ks < sv ? pass_weight(tab, Qv, K, tv, r16, 4 * ks + k4) : 0.0;
+    for (int nt = wave; nt * 16 < n2; nt += nwave) {
+        const int n = nt * 16 + r16;
+        const int k = n / Qw, c = n - (n / Qw) * Qw;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int ks = 0; ks < sv; ++ks) {
+            const int b = 4 * ks + k4;
+            const double x = (b < Qv && n < n2) ? P1[k * L + b * Qw + c] : 0.0;
+            if (tv) rec[13] = fmax(rec[13], fabs(x));
+            acc = mfma64(wa[ks], x, acc);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = 4 * i + k4;
+            if (n < n2) {
+                if (m < K) P2[(k * K + m) * QWS + c] = acc[i];
+                else if (tv && m < K + 4) rec[4 + m - K] = fmax(rec[4 + m - K], fabs(acc[i]));
+            }
+        }
+    }
+    __syncthreads();
+    // pass 3: contract w; columns n = (k, l); results staged in LDS so that
+    // the global write below is contiguous: in the P1 region (free after
+    // pass 2) when K^3 doubles fit below P2, else after P2 (the buffer is
+    // sized for that case)
     double *I = mom + d.mom_off + (int64_t)f * K * K * K;
-    for (int lq = tid; lq < K * K; lq += nt) {
-        const int l = lq / K, q = lq - (lq / K) * K;
-        double acc[K], tl[4] = {0.0, 0.0, 0.0, 0.0};
+    double *Is = (K * K * K <= p2off) ? sm : P2 + K * K * QWS;
+    const int sw = (Qw + 3) >> 2, n3 = K * K;
 #pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] = 0.0;
-        for (int a = 0; a < Qu; ++a) {
-            const double x = P2[(a * K + l) * KS + q];
+    for (int ks = 0; ks < MAXQ / 4; ++ks) wa[ks] = ks < sw ? pass_weight(tab, Qw, K, tw, r16, 4 * ks + k4) : 0.0;
+    for (int nt = wave; nt * 16 < n3; nt += nwave) {
+        const int n = nt * 16 + r16;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int ks = 0; ks < sw; ++ks) {
+            const int c = 4 * ks + k4;
+            const double x = (c < Qw && n < n3) ? P2[n * QWS + c] : 0.0;
+            if (tw) rec[14] = fmax(rec[14], fabs(x));
+            acc = mfma64(wa[ks], x, acc);
+        }
 #pragma unroll
-            for (int k = 0; k < K; ++k) acc[k] = fma(Wu[k * MAXQ + a], x, acc[k]);
-            if (tu) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) tl[j] = fma(Tu[j * MAXQ + a], x, tl[j]);
-                rec[12] = fmax(rec[12], fabs(x));
+        for (int i = 0; i < 4; ++i) {
+            const int m = 4 * i + k4;
+            if (n < n3) {
+                if (m < K) Is[n * K + m] = acc[i];
+                else if (tw && m < K + 4) rec[8 + m - K] = fmax(rec[8 + m - K], fabs(acc[i]));
             }
         }
-        if (tu)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) rec[j] = fmax(rec[j], fabs(tl[j]));
-#pragma unroll
-        for (int k = 0; k < K; ++k) I[k * K * K + lq] = acc[k];
     }
+    __syncthreads();
+    for (int i = tid; i < K * K * K; i += blockDim.x) I[i] = Is[i];
     if (TAIL) {
-        // block-wide maximum of the record: waves, then LDS (P1 is free now)
+        // block-wide maximum of the record: waves, then LDS (after the copy)
         __syncthreads();
-        const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
         for (int i = 0; i < 15; ++i) {
             const double v = wave_max(rec[i]);
@@ -313,7 +383,7 @@ __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const d
         __syncthreads();
         if (tid < 15) {
             double v = 0.0;
-            for (int w = 0; w < (nt + 63) / 64; ++w) v = fmax(v, sm[w * TAIL_REC + tid]);
+            for (int w = 0; w < nwave; ++w) v = fmax(v, sm[w * TAIL_REC + tid]);
             tailst[(e * F + f) * TAIL_REC + tid] = v;
         }
     }
@@ -330,30 +400,63 @@ __global__ __launch_bounds__(256) void k_moments(const ElemDesc *__restrict__ de
     const int64_t e = e0 + blockIdx.x;
     if (only && !only[e]) return;
     const ElemDesc d = desc[e];
-    const int f = blockIdx.y;
-    switch (d.N) {
-    case 2: moments_body<3, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
-    case 3: moments_body<5, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
-    case 4: moments_body<7, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
-    case 5: moments_body<9, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
-    case 6: moments_body<11, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
-    case 7: moments_body<13, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
-    case 8: moments_body<15, TAIL>(d, e, f, F, alpha, tab, mom, sm, p2off, tailst); break;
-    default: break;
+    if (TAIL && d.Qu >= MLP_KMAX && d.Qv >= MLP_KMAX && d.Qw >= MLP_KMAX) {
+        // nothing sampled below the full rule: plain moments, empty record
+        moments_body<false>(d, e, blockIdx.y, F, alpha, tab, mom, sm, p2off, tailst);
+        if (threadIdx.x < TAIL_REC) tailst[(e * F + blockIdx.y) * TAIL_REC + threadIdx.x] = 0.0;
+        return;
     }
+    moments_body<TAIL>(d, e, blockIdx.y, F, alpha, tab, mom, sm, p2off, tailst);
 }
 
 // LDS layout of k_moments for the largest order and rule of a plan:
-// P1 [Qu*Qv][KS] followed by P2 [Qu][K][KS], KS = K+1.
-int moments_p2_offset(int maxN, int maxQuv) { return maxQuv * (2 * maxN); }
-size_t moments_smem_bytes(int maxN, int maxQu, int maxQuv)
+// P1 [K][Qv*Qw] followed by P2 [K][K][Qw | 1]; the staged K^3 tile of
+// pass 3 reuses P1 when it fits there, else follows P2; at least 4 waves x
+// TAIL_REC doubles (the tail-record reduction reuses the start).
+int moments_p2_offset(int maxN, int maxQvw) { return maxQvw * (2 * maxN - 1); }
+size_t moments_smem_bytes(int maxN, int maxQw, int maxQvw)
 {
-    const int K = 2 * maxN - 1, KS = K + 1;
-    return sizeof(double) * (size_t)(moments_p2_offset(maxN, maxQuv) + maxQu * K * KS);
+    const int K = 2 * maxN - 1;
+    const size_t p2 = (size_t)moments_p2_offset(maxN, maxQvw);
+    size_t n = p2 + (size_t)(K * K * (maxQw | 1));
+    if ((size_t)(K * K * K) > p2) n += (size_t)(K * K * K);
+    return sizeof(double) * (n > 4 * TAIL_REC ? n : 4 * TAIL_REC);
 }
 
 // ---------------------------------------------------------------------------
 // Host-side launchers.
+
+template <int PROB, int KIND>
+static void launch_coupling_k(const ElemDesc *desc, int64_t e0, int64_t count, const double *nodes,
+                              const double *mat, int mat_stride, const double *tab, double *alpha,
+                              uint32_t *status, const int32_t *only, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_coupling<PROB, KIND>), dim3((unsigned)count), dim3(256), 0, st, desc, e0, nodes, mat,
+                       mat_stride, tab, alpha, status, only);
+}
+
+template <int PROB>
+static void launch_coupling_p(int kind, const ElemDesc *desc, int64_t e0, int64_t count, const double *nodes,
+                              const double *mat, int mat_stride, const double *tab, double *alpha,
+                              uint32_t *status, const int32_t *only, hipStream_t st)
+{
+    switch (kind) {
+    case MAT_SINCOSEXP:
+        launch_coupling_k<PROB, MAT_SINCOSEXP>(desc, e0, count, nodes, mat, mat_stride, tab, alpha, status, only, st);
+        break;
+    case MAT_ROTDIAG:
+        if constexpr (PROB == 1)
+            launch_coupling_k<PROB, MAT_ROTDIAG>(desc, e0, count, nodes, mat, mat_stride, tab, alpha, status, only,
+                                                 st);
+        break;
+    case MAT_PLANEWAVE:
+        launch_coupling_k<PROB, MAT_PLANEWAVE>(desc, e0, count, nodes, mat, mat_stride, tab, alpha, status, only, st);
+        break;
+    default:
+        launch_coupling_k<PROB, ALPHA_SAMPLED>(desc, e0, count, nodes, mat, mat_stride, tab, alpha, status, only, st);
+        break;
+    }
+}
 
 void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t count,
                      const double *nodes, const double *mat, int kind, int mat_stride,
@@ -361,14 +464,12 @@ void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t coun
 {
     if (count <= 0) return;
     if (problem == 0)
-        hipLaunchKernelGGL(k_coupling<0>, dim3((unsigned)count), dim3(256), 0, st, desc, e0, nodes,
-                           mat, kind, mat_stride, tab, alpha, status, only);
+        launch_coupling_p<0>(kind, desc, e0, count, nodes, mat, mat_stride, tab, alpha, status, only, st);
     else
-        hipLaunchKernelGGL(k_coupling<1>, dim3((unsigned)count), dim3(256), 0, st, desc, e0, nodes,
-                           mat, kind, mat_stride, tab, alpha, status, only);
+        launch_coupling_p<1>(kind, desc, e0, count, nodes, mat, mat_stride, tab, alpha, status, only, st);
 }
 
-void launch_moments(int problem, int maxN, int maxQu, int maxQuv, const ElemDesc *desc, int64_t e0,
+void launch_moments(int problem, int maxN, int maxQw, int maxQvw, const ElemDesc *desc, int64_t e0,
                     int64_t count, const double *alpha, const double *tab, double *mom, const int32_t *only,
                     double *tailst, hipStream_t st)
 {
@@ -376,12 +477,12 @@ void launch_moments(int problem, int maxN, int maxQu, int maxQuv, const ElemDesc
     const int F = num_fields(problem);
     if (tailst)
         hipLaunchKernelGGL(k_moments<true>, dim3((unsigned)count, F), dim3(256),
-                           moments_smem_bytes(maxN, maxQu, maxQuv), st, desc, e0, F, alpha, tab, mom,
-                           moments_p2_offset(maxN, maxQuv), only, tailst);
+                           moments_smem_bytes(maxN, maxQw, maxQvw), st, desc, e0, F, alpha, tab, mom,
+                           moments_p2_offset(maxN, maxQvw), only, tailst);
     else
         hipLaunchKernelGGL(k_moments<false>, dim3((unsigned)count, F), dim3(256),
-                           moments_smem_bytes(maxN, maxQu, maxQuv), st, desc, e0, F, alpha, tab, mom,
-                           moments_p2_offset(maxN, maxQuv), only, tailst);
+                           moments_smem_bytes(maxN, maxQw, maxQvw), st, desc, e0, F, alpha, tab, mom,
+                           moments_p2_offset(maxN, maxQvw), only, tailst);
 }
 
 int prepare_kernels()

@@ -23,20 +23,24 @@ def legendre_product_field(Qu, Qv, Qw, i, j, d):
 def test_records_of_a_legendre_product():
     Qu, Qv, Qw, N = 12, 10, 14, 8           # K_m = 15 covers every degree used
     i, j, d = Qu - 2, Qv - 1, Qw - 3
-    alpha, Li, Lj = legendre_product_field(Qu, Qv, Qw, i, j, d)
+    alpha, _, Lj = legendre_product_field(Qu, Qv, Qw, i, j, d)
     r = tail.records(alpha, Qu, Qv, Qw, N)[0]
-    m_ij = np.abs(np.outer(Li, Lj)).max()
-    cw, cv = 2.0 / (2 * d + 1), 2.0 / (2 * j + 1)
+    xw, _ = npleg.leggauss(Qw)
+    c = np.zeros(d + 1)
+    c[d] = 1.0
+    Ld = np.abs(npleg.legval(xw, c)).max()
+    m_jd = np.abs(Lj).max() * Ld
+    cu, cv = 2.0 / (2 * i + 1), 2.0 / (2 * j + 1)
     tol = 1e-13
-    # w: only degree Qw-3 is present, coefficient L_i L_j on every line
-    assert np.allclose(r[8:12], [0, 0, m_ij, 0], atol=tol, rtol=1e-12)
-    assert abs(r[14] - np.abs(alpha).max()) <= tol
-    # v: the w-moments are cw * L_i L_j at q = d only; degree Qv-1 on b
-    assert np.allclose(r[4:8], [cw * np.abs(Li).max(), 0, 0, 0], atol=tol, rtol=1e-12)
-    assert abs(r[13] - cw * m_ij) <= tol
-    # u: the (v,w)-moments are cv*cw*L_i at (l,q) = (j,d) only; degree Qu-2
-    assert np.allclose(r[0:4], [0, cv * cw, 0, 0], atol=tol, rtol=1e-12)
-    assert abs(r[12] - cv * cw * np.abs(Li).max()) <= tol
+    # u: only degree Qu-2 is present, coefficient L_j L_d on every line
+    assert np.allclose(r[0:4], [0, m_jd, 0, 0], atol=tol, rtol=1e-12)
+    assert abs(r[12] - np.abs(alpha).max()) <= tol
+    # v: the u-moments are cu * L_j L_d at k = i only; degree Qv-1 on b
+    assert np.allclose(r[4:8], [cu * Ld, 0, 0, 0], atol=tol, rtol=1e-12)
+    assert abs(r[13] - cu * m_jd) <= tol
+    # w: the (u,v)-moments are cu*cv*L_d at (k,l) = (i,j) only; degree Qw-3
+    assert np.allclose(r[8:12], [0, 0, cu * cv, 0], atol=tol, rtol=1e-12)
+    assert abs(r[14] - cu * cv * Ld) <= tol
     assert r[15] == 0.0
 
 
