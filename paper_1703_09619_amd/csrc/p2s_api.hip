@@ -51,7 +51,8 @@ struct p2s_plan_s {
     int64_t E = 0;
     bool uniform = true;
     int N = 0, Qu = 0, Qv = 0, Qw = 0;
-    int maxN = 0, maxQw = 0, maxQvw = 0;  // largest order and moment-stage LDS shape
+    int maxN = 0;
+    MomentShape mshape;  // largest order and rule sizes (moment-stage LDS)
     int mat_stride = 0;
     std::vector<int32_t> orders, quad;
     std::vector<int64_t> offsets;
@@ -315,8 +316,13 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
                             (long long)e, quad[3 * e + a], a, P2S_MAX_Q);
             }
         plan->maxN = std::max(plan->maxN, N);
-        plan->maxQw = std::max(plan->maxQw, (int)quad[3 * e + 2]);
-        plan->maxQvw = std::max(plan->maxQvw, (int)(quad[3 * e + 1] * quad[3 * e + 2]));
+        MomentShape &ms = plan->mshape;
+        ms.maxN = plan->maxN;
+        ms.maxQ = std::max({ms.maxQ, (int)quad[3 * e], (int)quad[3 * e + 1], (int)quad[3 * e + 2]});
+        ms.maxQu = std::max(ms.maxQu, (int)quad[3 * e]);
+        ms.maxQuv = std::max(ms.maxQuv, (int)(quad[3 * e] * quad[3 * e + 1]));
+        ms.maxQw = std::max(ms.maxQw, (int)quad[3 * e + 2]);
+        ms.maxQvw = std::max(ms.maxQvw, (int)(quad[3 * e + 1] * quad[3 * e + 2]));
         if (e > 0 && (N != orders[0] || quad[3 * e] != quad[0] || quad[3 * e + 1] != quad[1] ||
                       quad[3 * e + 2] != quad[2]))
             plan->uniform = false;
@@ -342,7 +348,8 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
         return fail(ctx, P2S_EQUAD, "plan: split-FP32 precision takes one order and one rule of at most %d points "
                                     "per axis for all elements", SPLIT_MAXQ);
     }
-    if (E > 0 && moments_smem_bytes(plan->maxN, plan->maxQw, plan->maxQvw) > LDS_LIMIT) {
+    if (E > 0 && (moments_lds_bytes(plan->mshape) > LDS_LIMIT ||
+                  moments_smem_bytes(plan->maxN, plan->mshape.maxQw, plan->mshape.maxQvw) > LDS_LIMIT)) {
         delete plan;
         return fail(ctx, P2S_EQUAD, "plan: rule too large for the moment stage at order %d", plan->maxN);
     }
@@ -497,7 +504,7 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
             launch_moments_split(problem, plan->d_desc, c.e0, c.count, plan->d_alpha, ctx->d_tab32,
                                  reinterpret_cast<float *>(plan->d_mom), st);
         else
-            launch_moments(problem, plan->maxN, plan->maxQw, plan->maxQvw, plan->d_desc, c.e0, c.count,
+            launch_moments(problem, plan->mshape, plan->d_desc, c.e0, c.count,
                            plan->d_alpha, ctx->d_tab, plan->d_mom, nullptr,
                            (learned || stop == STOP_TAILREC) ? plan->d_tailst : nullptr, st);
         prof_end(plan, 1, st);
@@ -509,7 +516,7 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
                                plan->d_redo, status, plan->d_tau, st);
             launch_coupling(problem, plan->d_desc, c.e0, c.count, nodes, material, plan->terms.material,
                             plan->mat_stride, ctx->d_tab, plan->d_alpha, status, plan->d_redo, st);
-            launch_moments(problem, plan->maxN, plan->maxQw, plan->maxQvw, plan->d_desc, c.e0, c.count,
+            launch_moments(problem, plan->mshape, plan->d_desc, c.e0, c.count,
                            plan->d_alpha, ctx->d_tab, plan->d_mom, plan->d_redo, nullptr, st);
             prof_end(plan, 3, st);
         }

@@ -11,16 +11,26 @@ namespace p2s {
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
 int prepare_kernels();
+// Largest order and rule sizes of a plan, for the moment stage's LDS.
+struct MomentShape {
+    int maxN = 0, maxQ = 0;    // order; points on any axis
+    int maxQu = 0, maxQuv = 0; // vector-unit form (rules of at most 16 points)
+    int maxQw = 0, maxQvw = 0; // matrix-core form
+};
 size_t moments_smem_bytes(int maxN, int maxQw, int maxQvw);
+size_t moments_lds_bytes(const MomentShape &m);  // of the form launch_moments picks without tail records
 
 // `only` (may be null): elements with only[e] == 0 are skipped; with it the
 // coupling kernel ORs its status bits instead of overwriting them.
 void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t count,
                      const double *nodes, const double *mat, int kind, int mat_stride,
                      const double *tab, double *alpha, uint32_t *status, const int32_t *only, hipStream_t st);
-void launch_moments(int problem, int maxN, int maxQw, int maxQvw, const ElemDesc *desc, int64_t e0,
-                    int64_t count, const double *alpha, const double *tab, double *mom, const int32_t *only,
-                    double *tailst, hipStream_t st);
+// Moment stage: the matrix-core form with tail records when tailst is
+// given, else the vector-unit form when every rule has at most 16 points,
+// else the matrix-core form.
+void launch_moments(int problem, const MomentShape &m, const ElemDesc *desc, int64_t e0, int64_t count,
+                    const double *alpha, const double *tab, double *mom, const int32_t *only, double *tailst,
+                    hipStream_t st);
 int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0,
                     int64_t count, const double *tab, const double *mom, double *out, uint32_t *status,
                     double sK, double sM, hipStream_t st);

@@ -409,6 +409,93 @@ __global__ __launch_bounds__(256) void k_moments(const ElemDesc *__restrict__ de
     moments_body<TAIL>(d, e, blockIdx.y, F, alpha, tab, mom, sm, p2off, tailst);
 }
 
+// Register-blocked vector-unit form of the same three passes (contract w,
+// then v, then u; one lane per line, K accumulators per lane), used when
+// every rule has at most 16 points: there the matrix-core tiles are few and
+// mostly padding, and this form is faster.  No tail statistic.
+template <int K>
+__device__ void moments_valu(const ElemDesc &d, int f, const double *__restrict__ alpha,
+                             const double *__restrict__ tab, double *__restrict__ mom, double *sm, int p2off)
+{
+    const int Qu = d.Qu, Qv = d.Qv, Qw = d.Qw;
+    const int P = Qu * Qv * Qw;
+    const double *A = alpha + d.alpha_off + (int64_t)f * P;
+    const double *Wu = tab + TAB_LEGW + Qu * LEGW_STRIDE_Q;
+    const double *Wv = tab + TAB_LEGW + Qv * LEGW_STRIDE_Q;
+    const double *Ww = tab + TAB_LEGW + Qw * LEGW_STRIDE_Q;
+    constexpr int KS = K + 1;  // LDS row stride
+    double *P1 = sm;          // [Qu*Qv][KS]   (q)
+    double *P2 = sm + p2off;  // [Qu][K][KS]   (l, q)
+    const int tid = threadIdx.x, nt = blockDim.x;
+    // pass 1: contract w
+    for (int ab = tid; ab < Qu * Qv; ab += nt) {
+        double acc[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] = 0.0;
+        const double *Ar = A + (int64_t)ab * Qw;
+        for (int c = 0; c < Qw; ++c) {
+            const double x = Ar[c];
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] = fma(Ww[q * MAXQ + c], x, acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) P1[ab * KS + q] = acc[q];
+    }
+    __syncthreads();
+    // pass 2: contract v
+    for (int aq = tid; aq < Qu * K; aq += nt) {
+        const int a = aq / K, q = aq - (aq / K) * K;
+        double acc[K];
+#pragma unroll
+        for (int l = 0; l < K; ++l) acc[l] = 0.0;
+        for (int b = 0; b < Qv; ++b) {
+            const double x = P1[(a * Qv + b) * KS + q];
+#pragma unroll
+            for (int l = 0; l < K; ++l) acc[l] = fma(Wv[l * MAXQ + b], x, acc[l]);
+        }
+#pragma unroll
+        for (int l = 0; l < K; ++l) P2[(a * K + l) * KS + q] = acc[l];
+    }
+    __syncthreads();
+    // pass 3: contract u
+    double *I = mom + d.mom_off + (int64_t)f * K * K * K;
+    for (int lq = tid; lq < K * K; lq += nt) {
+        const int l = lq / K, q = lq - (lq / K) * K;
+        double acc[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] = 0.0;
+        for (int a = 0; a < Qu; ++a) {
+            const double x = P2[(a * K + l) * KS + q];
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] = fma(Wu[k * MAXQ + a], x, acc[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) I[k * K * K + lq] = acc[k];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_moments_valu(const ElemDesc *__restrict__ desc, int64_t e0,
+                                                      const double *__restrict__ alpha,
+                                                      const double *__restrict__ tab, double *__restrict__ mom,
+                                                      int p2off, const int32_t *__restrict__ only)
+{
+    extern __shared__ double sm[];
+    const int64_t e = e0 + blockIdx.x;
+    if (only && !only[e]) return;
+    const ElemDesc d = desc[e];
+    const int f = blockIdx.y;
+    switch (d.N) {
+    case 2: moments_valu<3>(d, f, alpha, tab, mom, sm, p2off); break;
+    case 3: moments_valu<5>(d, f, alpha, tab, mom, sm, p2off); break;
+    case 4: moments_valu<7>(d, f, alpha, tab, mom, sm, p2off); break;
+    case 5: moments_valu<9>(d, f, alpha, tab, mom, sm, p2off); break;
+    case 6: moments_valu<11>(d, f, alpha, tab, mom, sm, p2off); break;
+    case 7: moments_valu<13>(d, f, alpha, tab, mom, sm, p2off); break;
+    case 8: moments_valu<15>(d, f, alpha, tab, mom, sm, p2off); break;
+    default: break;
+    }
+}
+
 // LDS layout of k_moments for the largest order and rule of a plan:
 // P1 [K][Qv*Qw] followed by P2 [K][K][Qw | 1]; the staged K^3 tile of
 // pass 3 reuses P1 when it fits there, else follows P2; at least 4 waves x
@@ -421,6 +508,18 @@ size_t moments_smem_bytes(int maxN, int maxQw, int maxQvw)
     size_t n = p2 + (size_t)(K * K * (maxQw | 1));
     if ((size_t)(K * K * K) > p2) n += (size_t)(K * K * K);
     return sizeof(double) * (n > 4 * TAIL_REC ? n : 4 * TAIL_REC);
+}
+// LDS layout of k_moments_valu: P1 [Qu*Qv][K+1] followed by P2 [Qu][K][K+1].
+static int valu_p2_offset(int maxN, int maxQuv) { return maxQuv * (2 * maxN); }
+static size_t valu_smem_bytes(int maxN, int maxQu, int maxQuv)
+{
+    const int K = 2 * maxN - 1;
+    return sizeof(double) * (size_t)(valu_p2_offset(maxN, maxQuv) + maxQu * K * (K + 1));
+}
+size_t moments_lds_bytes(const MomentShape &m)
+{
+    return m.maxQ <= SPLIT_MAXQ ? valu_smem_bytes(m.maxN, m.maxQu, m.maxQuv)
+                                : moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw);
 }
 
 // ---------------------------------------------------------------------------
@@ -469,20 +568,24 @@ void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t coun
         launch_coupling_p<1>(kind, desc, e0, count, nodes, mat, mat_stride, tab, alpha, status, only, st);
 }
 
-void launch_moments(int problem, int maxN, int maxQw, int maxQvw, const ElemDesc *desc, int64_t e0,
-                    int64_t count, const double *alpha, const double *tab, double *mom, const int32_t *only,
-                    double *tailst, hipStream_t st)
+void launch_moments(int problem, const MomentShape &m, const ElemDesc *desc, int64_t e0, int64_t count,
+                    const double *alpha, const double *tab, double *mom, const int32_t *only, double *tailst,
+                    hipStream_t st)
 {
     if (count <= 0) return;
     const int F = num_fields(problem);
     if (tailst)
         hipLaunchKernelGGL(k_moments<true>, dim3((unsigned)count, F), dim3(256),
-                           moments_smem_bytes(maxN, maxQw, maxQvw), st, desc, e0, F, alpha, tab, mom,
-                           moments_p2_offset(maxN, maxQvw), only, tailst);
+                           moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw), st, desc, e0, F, alpha, tab, mom,
+                           moments_p2_offset(m.maxN, m.maxQvw), only, tailst);
+    else if (m.maxQ <= SPLIT_MAXQ)
+        hipLaunchKernelGGL(k_moments_valu, dim3((unsigned)count, F), dim3(256),
+                           valu_smem_bytes(m.maxN, m.maxQu, m.maxQuv), st, desc, e0, alpha, tab, mom,
+                           valu_p2_offset(m.maxN, m.maxQuv), only);
     else
         hipLaunchKernelGGL(k_moments<false>, dim3((unsigned)count, F), dim3(256),
-                           moments_smem_bytes(maxN, maxQw, maxQvw), st, desc, e0, F, alpha, tab, mom,
-                           moments_p2_offset(maxN, maxQvw), only, tailst);
+                           moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw), st, desc, e0, F, alpha, tab, mom,
+                           moments_p2_offset(m.maxN, m.maxQvw), only, tailst);
 }
 
 int prepare_kernels()
@@ -492,7 +595,9 @@ int prepare_kernels()
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     hipError_t r2 = hipFuncSetAttribute((const void *)k_moments<true>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    return r == hipSuccess && r2 == hipSuccess ? 0 : -1;
+    hipError_t r3 = hipFuncSetAttribute((const void *)k_moments_valu,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    return r == hipSuccess && r2 == hipSuccess && r3 == hipSuccess ? 0 : -1;
 }
 
 }  // namespace p2s
