@@ -327,18 +327,35 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                 double *drow = obase + (int64_t)(rowbase + n1a * NP_I) * NDOF + colj;
                 const bool d16 = (NDOF % 2 == 0) && (W % 2 == 0) &&
                                  ((reinterpret_cast<uintptr_t>(drow) & 15u) == 0);
+                // the element index x = tid + i*nthreads of an (r, c) grid of
+                // width wd is walked incrementally: one division per thread
+                // and phase instead of one per stored element
                 if (d16) {
-                    const int hw = W / 2;
-                    for (int x = tid; x < nr * hw; x += nthreads) {
-                        const int r = x / hw, c = 2 * (x - r * hw);
+                    const int hw = W / 2, dr = nthreads / hw, dc = nthreads - dr * hw;
+                    int r = tid / hw, h = tid - r * hw;
+                    while (r < nr) {
+                        const int c = 2 * h;
                         // two 8-byte LDS reads (rows are only 8-byte aligned)
                         *reinterpret_cast<double2 *>(drow + (int64_t)r * NDOF + c) =
                             make_double2(smem[r * WS + c], smem[r * WS + c + 1]);
+                        r += dr;
+                        h += dc;
+                        if (h >= hw) {
+                            h -= hw;
+                            ++r;
+                        }
                     }
                 } else {
-                    for (int x = tid; x < nr * W; x += nthreads) {
-                        const int r = x / W, c = x - r * W;
+                    const int dr = nthreads / W, dc = nthreads - dr * W;
+                    int r = tid / W, c = tid - r * W;
+                    while (r < nr) {
                         drow[(int64_t)r * NDOF + c] = smem[r * WS + c];
+                        r += dr;
+                        c += dc;
+                        if (c >= W) {
+                            c -= W;
+                            ++r;
+                        }
                     }
                 }
                 // mirror: tile column c is output row colj + c, holding the nr
@@ -348,16 +365,31 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                 const bool m16 = (NDOF % 2 == 0) && (nr % 2 == 0) &&
                                  ((reinterpret_cast<uintptr_t>(mrow) & 15u) == 0);
                 if (m16) {
-                    const int hr = nr / 2;
-                    for (int x = tid; x < nc * hr; x += nthreads) {
-                        const int c = cmir + x / hr, r = 2 * (x - (x / hr) * hr);
+                    const int hr = nr / 2, dq = nthreads / hr, dh = nthreads - dq * hr;
+                    int q = tid / hr, h = tid - q * hr;  // tile column cmir + q, row pair h
+                    while (q < nc) {
+                        const int c = cmir + q, r = 2 * h;
                         *reinterpret_cast<double2 *>(mrow + (int64_t)c * NDOF + r) =
                             make_double2(smem[r * WS + c], smem[(r + 1) * WS + c]);
+                        q += dq;
+                        h += dh;
+                        if (h >= hr) {
+                            h -= hr;
+                            ++q;
+                        }
                     }
                 } else {
-                    for (int x = tid; x < nc * nr; x += nthreads) {
-                        const int c = cmir + x / nr, r = x - (x / nr) * nr;
+                    const int dq = nthreads / nr, dh = nthreads - dq * nr;
+                    int q = tid / nr, r = tid - q * nr;
+                    while (q < nc) {
+                        const int c = cmir + q;
                         mrow[(int64_t)c * NDOF + r] = smem[r * WS + c];
+                        q += dq;
+                        r += dh;
+                        if (r >= nr) {
+                            r -= nr;
+                            ++q;
+                        }
                     }
                 }
                 __syncthreads();
