@@ -1,6 +1,6 @@
 """GPU tests of the learned quadrature order: the network kernels against
 the FP64 CPU reference (oracle/mlp.py), the order choice, training, and the
-learned fill (fallback and accuracy judged by the full-rule fill)."""
+learned fill (fallback, and accuracy measured against the full-rule fill)."""
 import math
 import os
 
