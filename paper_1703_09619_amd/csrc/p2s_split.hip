@@ -241,23 +241,25 @@ __global__ __launch_bounds__(256) void k_contract_split(const ElemDesc *__restri
             for (int i = 0; i < 4; ++i)
                 tile[(16 * wave + 4 * k4 + i) * SPLIT_TILE_STRIDE + nt * 16 + r16] = acc[nt * 4 + i];
         __syncthreads();
-        // rows (n1,p1) of m1 against columns (n2,p2) of m2
+        // rows (n1,p1) of m1 against columns (n2,p2) of m2.  Threads take a
+        // padded 8x8 grid: the low six bits of the thread id give the
+        // contiguous pair of a row, the high bits the row (four per pass), so
+        // the index arithmetic is shifts and masks only.
         const int colbase = comp_offset(PROB, N, J) + m2 * NN_J * NP_J;
-        const int ncol = NN_J * NP_J, nrow = NN_I * NP_I;
-        for (int x = threadIdx.x; x < nrow * ncol; x += blockDim.x) {
-            const int r = x / ncol, cidx = x - r * ncol;
-            const int n1 = r / NP_I, p1 = r - n1 * NP_I, n2 = cidx / NP_J, p2 = cidx - n2 * NP_J;
-            const double v = tile[(n1 * 8 + n2) * SPLIT_TILE_STRIDE + p1 * 8 + p2];
-            bad |= !isfinite(v);
-            obase[(int64_t)(rowbase + r) * NDOF + colbase + cidx] = v;
-        }
-        if (J != I || m2 != m1) {
-            // mirror: row colbase + (n2,p2), columns rowbase + (n1,p1)
-            for (int x = threadIdx.x; x < nrow * ncol; x += blockDim.x) {
-                const int cidx = x / nrow, r = x - cidx * nrow;
-                const int n1 = r / NP_I, p1 = r - n1 * NP_I, n2 = cidx / NP_J, p2 = cidx - n2 * NP_J;
-                obase[(int64_t)(colbase + cidx) * NDOF + rowbase + r] =
-                    tile[(n1 * 8 + n2) * SPLIT_TILE_STRIDE + p1 * 8 + p2];
+        {
+            const int t = threadIdx.x & 63, ta = t >> 3, tb = t & 7;  // (n2,p2) / (n1,p1) of the thread
+            for (int rr = threadIdx.x >> 6; rr < 64; rr += blockDim.x >> 6) {
+                const int ra = rr >> 3, rb = rr & 7;                  // (n1,p1) / (n2,p2) of the row
+                // direct: row (n1,p1) = (ra,rb), column (n2,p2) = (ta,tb)
+                if (ra < NN_I && rb < NP_I && ta < NN_J && tb < NP_J) {
+                    const double v = tile[(ra * 8 + ta) * SPLIT_TILE_STRIDE + rb * 8 + tb];
+                    bad |= !isfinite(v);
+                    obase[(int64_t)(rowbase + ra * NP_I + rb) * NDOF + colbase + ta * NP_J + tb] = v;
+                }
+                // mirror: row colbase + (n2,p2) = (ra,rb) of J, column rowbase + (n1,p1) = (ta,tb) of I
+                if ((J != I || m2 != m1) && ra < NN_J && rb < NP_J && ta < NN_I && tb < NP_I)
+                    obase[(int64_t)(colbase + ra * NP_J + rb) * NDOF + rowbase + ta * NP_I + tb] =
+                        tile[(ta * 8 + ra) * SPLIT_TILE_STRIDE + tb * 8 + rb];
             }
         }
         __syncthreads();
