@@ -2,11 +2,11 @@
 // eq. (4) of the paper: M = sum_s sum_{k,l,q} Cu Cv Cw I_s, applied mode by
 // mode, for gfx950 (wave64).
 //
-// One workgroup per (element, row component I, first-axis test index m1):
-// it produces rows (m1, n1, p1) of component I against column components
-// J >= I (the element matrix is symmetric; the part below the diagonal is
-// stored as the mirror image).  For a block (I,J) the coupling terms are
-// grouped: a group shares the (v, w) family pairs, a run shares the w pair.
+// One kernel per component block (I, J >= I) and one workgroup per (element,
+// first-axis test index m1): it produces rows (m1, n1, p1) of component I
+// against component J (the element matrix is symmetric; the part below the
+// diagonal is stored as the mirror image).  Within a block the coupling terms are grouped: a group shares the (v, w)
+// family pairs, a run shares the w pair.
 //   stage A  A_g[m2][l][q] = sum_{s in g} sign_s sum_k Cu_s[m1][m2][k] I_s[k][l][q]
 //            one thread per (group, l, q); each moment is loaded once and
 //            reused for every m2                                     (LDS)
@@ -160,10 +160,10 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t total_padded)
 }
 
 // One work item: rows (m1, n1, p1) of component I of element e against the
-// column components J >= I.  Called by all `nthreads` threads of a
+// column components JB <= J < JE (JB >= I).  Called by all `nthreads` threads of a
 // workgroup (nthreads >= THREADS; extra threads take part in the barriers
 // and the cooperative loops only).  smem holds at least BUF doubles.
-template <int PROB, int N, int I>
+template <int PROB, int N, int I, int JB = I, int JE = num_comp(PROB)>
 __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int m1,
                                               const double *__restrict__ tab, const double *__restrict__ mom,
                                               double *__restrict__ out, uint32_t *__restrict__ status,
@@ -180,7 +180,7 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
     const int rowbase = comp_offset(PROB, N, I) + m1 * NN_I * NP_I;
     bool bad = false;
 
-    static_for<I, NC>([&](auto Jc) {
+    static_for<JB, JE>([&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
         constexpr BlockC BK = BlockOf<PROB, I, J>::B;
         constexpr int NM_J = comp_dim(PROB, N, J, 0), NN_J = comp_dim(PROB, N, J, 1),
@@ -399,7 +399,11 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
     if (__syncthreads_or(bad) && tid == 0) atomicOr(status + e, P2S_STATUS_NONFINITE_BIT);
 }
 
-template <int PROB, int N, int I>
+// One launch per column block (I, J >= I): each kernel holds the code of a
+// single block, which keeps it within the instruction cache (a kernel with
+// all three column blocks of I = 0 missed in it two orders of magnitude more
+// often than one with a single block).
+template <int PROB, int N, int I, int J>
 __global__ __launch_bounds__((CS<PROB, N, I>::THREADS), (N <= 6 ? 3 : 2)) void k_contract(
     const ElemDesc *__restrict__ desc, const int32_t *__restrict__ elist, int64_t e0, int64_t nitems,
     int64_t padded, const double *__restrict__ tab, const double *__restrict__ mom,
@@ -413,10 +417,10 @@ __global__ __launch_bounds__((CS<PROB, N, I>::THREADS), (N <= 6 ? 3 : 2)) void k
     const int m1 = (int)(item % S::NM_I);
     const ElemDesc d = desc[e];
     __shared__ __attribute__((aligned(16))) double smem[S::BUF];
-    contract_item<PROB, N, I>(d, e, m1, tab, mom, out, status, sK, sM, smem, S::THREADS);
+    contract_item<PROB, N, I, J, J + 1>(d, e, m1, tab, mom, out, status, sK, sM, smem, S::THREADS);
 }
 
-template <int PROB, int N, int I>
+template <int PROB, int N, int I, int J>
 static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,
                               const double *tab, const double *mom, double *out, uint32_t *status,
                               double sK, double sM, hipStream_t st)
@@ -424,7 +428,7 @@ static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_
     using S = CS<PROB, N, I>;
     const int64_t nitems = count * S::NM_I;
     const int64_t padded = (nitems + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_contract<PROB, N, I>), dim3((unsigned)padded), dim3(S::THREADS), 0, st, desc,
+    hipLaunchKernelGGL((k_contract<PROB, N, I, J>), dim3((unsigned)padded), dim3(S::THREADS), 0, st, desc,
                        elist, e0, nitems, padded, tab, mom, out, status, sK, sM);
 }
 
@@ -504,10 +508,13 @@ static void launch_contract_t(const ElemDesc *desc, const int32_t *elist, int64_
                               const double *tab, const double *mom, double *out, uint32_t *status,
                               double sK, double sM, hipStream_t st)
 {
-    launch_contract_i<PROB, N, 0>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+    launch_contract_i<PROB, N, 0, 0>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
     if constexpr (PROB == 1) {
-        launch_contract_i<PROB, N, 1>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
-        launch_contract_i<PROB, N, 2>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+        launch_contract_i<PROB, N, 0, 1>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+        launch_contract_i<PROB, N, 0, 2>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+        launch_contract_i<PROB, N, 1, 1>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+        launch_contract_i<PROB, N, 1, 2>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+        launch_contract_i<PROB, N, 2, 2>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
     }
 }
 
