@@ -152,8 +152,8 @@ def main():
     st = status.cpu().numpy()
 
     # dominant kernel: the contraction stage (HIP events on the launch stream
-    # around the stage's launches: one kernel per row component, or one
-    # persistent kernel, or one kernel per block in the split form)
+    # around the stage's launches: one kernel per component block, or one
+    # persistent kernel for mixed orders)
     c_ms, c_segments = stages["contraction"]
     if w.problem == 0 and len(set(w.orders.tolist())) > 1:
         alg_bytes = sum(contract_bytes_per_element(0, int(n)) for n in w.orders)
@@ -167,8 +167,8 @@ def main():
     elif not n_uniform:
         kname, per_chunk = "k_contract_persistent_scalar", 1
     else:
-        kname = "k_contract<%d,%d,I> (row components I)" % (w.problem, int(w.orders[0]))
-        per_chunk = 3 if w.problem else 1
+        kname = "k_contract<%d,%d,I,J> (blocks J >= I)" % (w.problem, int(w.orders[0]))
+        per_chunk = 6 if w.problem else 1
     traffic = measured_traffic(args.workload, args.precision)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
