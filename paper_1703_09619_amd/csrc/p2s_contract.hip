@@ -104,9 +104,10 @@ struct CS {
     static constexpr int A_DOUBLES = N * K * KS;                    // stage-A result per group
     static constexpr int C_DOUBLES = NN_I * max_over_j(2) * KS;      // stage-B coefficients per group
     static constexpr int GROUP_DOUBLES = A_DOUBLES + C_DOUBLES;
-    // groups per LDS batch: ~52 KiB up to N = 6 (three workgroups per CU,
-    // with at most 168 VGPRs, see k_contract), ~62 KiB above
-    static constexpr int G = cmax(1, cmin(MAXG, (N <= 6 ? 6656 : 7936) / GROUP_DOUBLES));
+    // groups per LDS batch: at most 40 KiB up to N = 6, so that four
+    // three-wave workgroups share a CU (the 168-VGPR bound of k_contract
+    // allows twelve waves per CU), ~62 KiB above
+    static constexpr int G = cmax(1, cmin(MAXG, (N <= 6 ? 5120 : 7936) / GROUP_DOUBLES));
     static constexpr int TILE_MIN = (max_over_j(3) + 2) * NP_I;     // one n1 of the store tile
     static constexpr int BUF = cmax(G * GROUP_DOUBLES, TILE_MIN);
     static constexpr int SA = ((K * K + 63) / 64) * 64;              // stage-A workers per group
