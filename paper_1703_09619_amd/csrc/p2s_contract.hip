@@ -77,7 +77,9 @@ constexpr PackOffsets kPackOffsets = PackOffsets();
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
-template <int PROB, int N, int I>
+// Compile-time shape of the work item of row component I against the column
+// components JB <= J < JE: lane count, LDS batching and store tile.
+template <int PROB, int N, int I, int JB = I, int JE = num_comp(PROB)>
 struct CS {
     static constexpr int K = 2 * N - 1;
     static constexpr int KS = K + 1;  // LDS row stride (16-byte aligned rows)
@@ -89,7 +91,7 @@ struct CS {
     static constexpr int max_over_j(int what)
     {
         int m = 0;
-        for (int j = I; j < NC; ++j) {
+        for (int j = JB; j < JE; ++j) {
             int v = 0;
             if (what == 0) v = comp_dim(PROB, N, j, 0) * NN_I * comp_dim(PROB, N, j, 1);  // lane tasks
             if (what == 1) v = make_block_c(PROB, I, j).ngroup;
@@ -170,7 +172,7 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                                               double *__restrict__ out, uint32_t *__restrict__ status,
                                               double sK, double sM, double *__restrict__ smem, int nthreads)
 {
-    using S = CS<PROB, N, I>;
+    using S = CS<PROB, N, I, JB, JE>;
     constexpr int K = S::K, KS = S::KS, NC = S::NC, NDOF = S::NDOF, G = S::G;
     constexpr int NN_I = S::NN_I, NP_I = S::NP_I;
     const double *lin = tab + TAB_LIN;
@@ -405,12 +407,12 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
 // all three column blocks of I = 0 missed in it two orders of magnitude more
 // often than one with a single block).
 template <int PROB, int N, int I, int J>
-__global__ __launch_bounds__((CS<PROB, N, I>::THREADS), (N <= 6 ? 3 : 2)) void k_contract(
+__global__ __launch_bounds__((CS<PROB, N, I, J, J + 1>::THREADS), (N <= 6 ? 3 : 2)) void k_contract(
     const ElemDesc *__restrict__ desc, const int32_t *__restrict__ elist, int64_t e0, int64_t nitems,
     int64_t padded, const double *__restrict__ tab, const double *__restrict__ mom,
     double *__restrict__ out, uint32_t *__restrict__ status, double sK, double sM)
 {
-    using S = CS<PROB, N, I>;
+    using S = CS<PROB, N, I, J, J + 1>;
     const int64_t item = xcd_remap(blockIdx.x, padded);
     if (item >= nitems) return;
     const int64_t eidx = e0 + item / S::NM_I;
@@ -426,7 +428,7 @@ static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_
                               const double *tab, const double *mom, double *out, uint32_t *status,
                               double sK, double sM, hipStream_t st)
 {
-    using S = CS<PROB, N, I>;
+    using S = CS<PROB, N, I, J, J + 1>;
     const int64_t nitems = count * S::NM_I;
     const int64_t padded = (nitems + 7) / 8 * 8;
     hipLaunchKernelGGL((k_contract<PROB, N, I, J>), dim3((unsigned)padded), dim3(S::THREADS), 0, st, desc,
