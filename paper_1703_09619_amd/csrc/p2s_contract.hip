@@ -97,6 +97,7 @@ struct CS {
             if (what == 1) v = make_block_c(PROB, I, j).ngroup;
             if (what == 2) v = comp_dim(PROB, N, j, 1);
             if (what == 3) v = comp_dim(PROB, N, j, 0) * comp_dim(PROB, N, j, 1) * comp_dim(PROB, N, j, 2);
+            if (what == 4) v = comp_dim(PROB, N, j, 1) * comp_dim(PROB, N, j, 2);
             m = cmax(m, v);
         }
         return m;
@@ -110,7 +111,7 @@ struct CS {
     // three-wave workgroups share a CU (the 168-VGPR bound of k_contract
     // allows twelve waves per CU), ~62 KiB above
     static constexpr int G = cmax(1, cmin(MAXG, (N <= 6 ? 5120 : 7936) / GROUP_DOUBLES));
-    static constexpr int TILE_MIN = (max_over_j(3) + 2) * NP_I;     // one n1 of the store tile
+    static constexpr int TILE_MIN = NN_I * NP_I * (max_over_j(4) + 2);  // one m2 of the store tile
     static constexpr int BUF = cmax(G * GROUP_DOUBLES, TILE_MIN);
     static constexpr int SA = ((K * K + 63) / 64) * 64;              // stage-A workers per group
 };
@@ -301,23 +302,23 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
             __syncthreads();
         });
 
-        // coalesced stores through LDS: the tile holds rows (n1, p1) and
-        // columns (m2, n2, p2), m2 >= m2lo; n1 goes in chunks that fit
+        // coalesced stores through LDS: the tile holds all rows (n1, p1) of
+        // the item and the columns (m2, n2, p2) of a chunk of m2 >= m2lo, so
+        // that every mirrored row segment (the item's NR values) is written
+        // whole by one workgroup in one pass
         {
-            const int W = nm * NN_J * NP_J;     // tile width
-            // odd row stride: the transposed (mirror) reads below step two rows
-            // per lane, which an odd stride spreads over distinct LDS banks
-            const int WS = W | 1;
-            int cn = S::BUF / (WS * NP_I);
-            cn = cn < 1 ? 1 : cn;
-            const int colj = comp_offset(PROB, N, J) + m2lo * NN_J * NP_J;
-            // mirrored rows start after the diagonal slab m2 == m1 of block (I,I)
-            const int cmir = (J == I) ? NN_J * NP_J : 0;
-            for (int n1a = 0; n1a < NN_I; n1a += cn) {
-                const int n1b = n1a + cn < NN_I ? n1a + cn : NN_I;
-                const int nr = (n1b - n1a) * NP_I;
-                if (active && n1 >= n1a && n1 < n1b) {
-                    double *tl = smem + (n1 - n1a) * NP_I * WS + ((m2 - m2lo) * NN_J + n2) * NP_J;
+            constexpr int NR = NN_I * NP_I;      // tile rows
+            constexpr int CW = NN_J * NP_J;      // tile columns per m2
+            constexpr int CM = cmax(1, (S::BUF / NR - 1) / CW);  // m2 per chunk
+            static_assert(NR * ((CM * CW) | 1) <= S::BUF, "store tile exceeds the LDS buffer");
+            for (int ma = m2lo; ma < NM_J; ma += CM) {
+                const int mb = ma + CM < NM_J ? ma + CM : NM_J;
+                const int W = (mb - ma) * CW;    // tile width
+                // odd row stride: the transposed (mirror) reads below step two
+                // rows per lane, which an odd stride spreads over distinct banks
+                const int WS = W | 1;
+                if (active && m2 >= ma && m2 < mb) {
+                    double *tl = smem + n1 * NP_I * WS + ((m2 - ma) * NN_J + n2) * NP_J;
 #pragma unroll
                     for (int p1 = 0; p1 < NP_I; ++p1)
 #pragma unroll
@@ -327,7 +328,10 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                         }
                 }
                 __syncthreads();
-                double *drow = obase + (int64_t)(rowbase + n1a * NP_I) * NDOF + colj;
+                const int colj = comp_offset(PROB, N, J) + ma * CW;
+                // mirrored rows start after the diagonal slab m2 == m1 of block (I,I)
+                const int cmir = (J == I && ma == m2lo) ? CW : 0;
+                double *drow = obase + (int64_t)rowbase * NDOF + colj;
                 const bool d16 = (NDOF % 2 == 0) && (W % 2 == 0) &&
                                  ((reinterpret_cast<uintptr_t>(drow) & 15u) == 0);
                 // the element index x = tid + i*nthreads of an (r, c) grid of
@@ -336,7 +340,7 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                 if (d16) {
                     const int hw = W / 2, dr = nthreads / hw, dc = nthreads - dr * hw;
                     int r = tid / hw, h = tid - r * hw;
-                    while (r < nr) {
+                    while (r < NR) {
                         const int c = 2 * h;
                         // two 8-byte LDS reads (rows are only 8-byte aligned)
                         *reinterpret_cast<double2 *>(drow + (int64_t)r * NDOF + c) =
@@ -351,7 +355,7 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                 } else {
                     const int dr = nthreads / W, dc = nthreads - dr * W;
                     int r = tid / W, c = tid - r * W;
-                    while (r < nr) {
+                    while (r < NR) {
                         drow[(int64_t)r * NDOF + c] = smem[r * WS + c];
                         r += dr;
                         c += dc;
@@ -361,14 +365,14 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                         }
                     }
                 }
-                // mirror: tile column c is output row colj + c, holding the nr
-                // contiguous values of columns rowbase + n1a*NP_I + r
-                double *mrow = obase + (int64_t)colj * NDOF + rowbase + n1a * NP_I;
+                // mirror: tile column c is output row colj + c, holding the NR
+                // contiguous values of columns rowbase + r
+                double *mrow = obase + (int64_t)colj * NDOF + rowbase;
                 const int nc = W - cmir;
-                const bool m16 = (NDOF % 2 == 0) && (nr % 2 == 0) &&
+                const bool m16 = (NDOF % 2 == 0) && (NR % 2 == 0) &&
                                  ((reinterpret_cast<uintptr_t>(mrow) & 15u) == 0);
                 if (m16) {
-                    const int hr = nr / 2, dq = nthreads / hr, dh = nthreads - dq * hr;
+                    const int hr = NR / 2, dq = nthreads / hr, dh = nthreads - dq * hr;
                     int q = tid / hr, h = tid - q * hr;  // tile column cmir + q, row pair h
                     while (q < nc) {
                         const int c = cmir + q, r = 2 * h;
@@ -382,15 +386,15 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                         }
                     }
                 } else {
-                    const int dq = nthreads / nr, dh = nthreads - dq * nr;
-                    int q = tid / nr, r = tid - q * nr;
+                    const int dq = nthreads / NR, dh = nthreads - dq * NR;
+                    int q = tid / NR, r = tid - q * NR;
                     while (q < nc) {
                         const int c = cmir + q;
                         mrow[(int64_t)c * NDOF + r] = smem[r * WS + c];
                         q += dq;
                         r += dh;
-                        if (r >= nr) {
-                            r -= nr;
+                        if (r >= NR) {
+                            r -= NR;
                             ++q;
                         }
                     }
