@@ -102,7 +102,11 @@ struct CS {
         }
         return m;
     }
-    static constexpr int THREADS = ((max_over_j(0) + 63) / 64) * 64;
+    // stage-B lanes in whole waves; from N = 7 on a CU holds a single
+    // workgroup, so whole groups of four waves keep its four SIMDs evenly
+    // loaded (and stage A's workers of two groups fit one pass)
+    static constexpr int THREADS =
+        N <= 6 ? ((max_over_j(0) + 63) / 64) * 64 : ((max_over_j(0) + 255) / 256) * 256;
     static constexpr int MAXG = max_over_j(1);
     static constexpr int A_DOUBLES = N * K * KS;                    // stage-A result per group
     static constexpr int C_DOUBLES = NN_I * max_over_j(2) * KS;      // stage-B coefficients per group
