@@ -136,6 +136,15 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    schedule = None
+    if len(set(w.orders.tolist())) > 1 and not split:
+        # mixed orders: the schedule autotuner picks per-order-class launches
+        # or the persistent launch (outside the timed region)
+        plan.autotune(nodes, mat, out, status)
+        mode, wpc = plan.schedule()
+        schedule = {"mode": "per_order_class" if mode == 0 else "persistent", "wgs_per_cu": wpc,
+                    "chosen_by": "p2s_plan_autotune"}
+
     for _ in range(args.warmup):
         plan.execute(nodes, mat, out, status)
     torch.cuda.synchronize()
@@ -152,8 +161,8 @@ def main():
     st = status.cpu().numpy()
 
     # dominant kernel: the contraction stage (HIP events on the launch stream
-    # around the stage's launches: one kernel per component block, or one
-    # persistent kernel for mixed orders)
+    # around the stage's launches: one kernel per component block, per order
+    # class for mixed orders, or one persistent kernel)
     c_ms, c_segments = stages["contraction"]
     if w.problem == 0 and len(set(w.orders.tolist())) > 1:
         alg_bytes = sum(contract_bytes_per_element(0, int(n)) for n in w.orders)
@@ -164,8 +173,10 @@ def main():
     n_uniform = len(set(w.orders.tolist())) == 1
     if split:
         kname, per_chunk = "k_contract_split<%d,I,J> (blocks J >= I)" % w.problem, 6 if w.problem else 1
-    elif not n_uniform:
+    elif not n_uniform and schedule["mode"] == "persistent":
         kname, per_chunk = "k_contract_persistent_scalar", 1
+    elif not n_uniform:
+        kname, per_chunk = "k_contract<0,N,0,0> (one launch per order N)", len(set(w.orders.tolist()))
     else:
         kname = "k_contract<%d,%d,I,J> (blocks J >= I)" % (w.problem, int(w.orders[0]))
         per_chunk = 6 if w.problem else 1
@@ -220,7 +231,8 @@ def main():
         "dtype": "f32 (hi/lo split operands) + f64" if split else "f64",
         "data": "synthetic (seeded curved triquadratic hexahedra and analytic materials)",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "elements": w.E,
-                   "orders": sorted(set(int(n) for n in w.orders)), "gauss_points": w.quad[0].tolist()},
+                   "orders": sorted(set(int(n) for n in w.orders)), "gauss_points": w.quad[0].tolist(),
+                   **({"schedule": schedule} if schedule else {})},
         "roofline": roofline,
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "status_nonzero": int((st != 0).sum()),

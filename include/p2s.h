@@ -156,11 +156,11 @@ int p2s_plan_profile(p2s_plan plan, int enable);
 int p2s_plan_profile_read(p2s_plan plan, double *ms, int64_t *launches);
 
 /* Schedule of the contraction stage.  mode 0: one launch per order class
- * (per row component for the vector problem), one workgroup per row tile;
- * mode 1 (scalar problem): one persistent launch of wgs_per_cu workgroups
- * per compute unit that take row tiles from a list sorted by decreasing
- * cost (longest first) through an atomic counter.  Plans of mixed orders of
- * the scalar problem start in mode 1, others in mode 0. */
+ * (per component block J >= I for the vector problem), one workgroup per
+ * row tile; mode 1 (scalar problem): one persistent launch of wgs_per_cu
+ * workgroups per compute unit that take row tiles from a list sorted by
+ * decreasing cost (longest first) through an atomic counter.  Every plan
+ * starts in mode 0; p2s_plan_autotune chooses between them. */
 int p2s_plan_set_schedule(p2s_plan plan, int mode, int wgs_per_cu);
 int p2s_plan_get_schedule(p2s_plan plan, int *mode, int *wgs_per_cu);
 

@@ -437,11 +437,10 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
     }
     plan->bytes = (int64_t)(sizeof(ElemDesc) * E + 8 * (plan->alpha_cap + plan->mom_cap) + 4 * elist.size() +
                             sizeof(WorkItem) * items.size());
-    // mixed orders of the scalar problem default to the persistent schedule
-    if (!plan->uniform && problem == P2S_SCALAR) {
-        plan->mode = 1;
-        plan->wpc = 1;
-    }
+    // every plan starts with the per-order-class launches: each order runs
+    // its own kernel at that kernel's occupancy, while the persistent kernel
+    // holds the bodies of all orders and runs one 512-lane workgroup per
+    // compute unit (p2s_plan_autotune times both)
     plan->desc_host = desc;
     if (E > 0) {
         if (hipMemcpy(plan->d_desc, desc.data(), sizeof(ElemDesc) * E, hipMemcpyHostToDevice) != hipSuccess ||

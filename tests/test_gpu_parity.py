@@ -238,9 +238,10 @@ def test_persistent_schedule_matches_per_class(env):
     torch, W = env["torch"], env["W"]
     w = W.make("scalar_mixed", E=300)
     plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
-    assert plan.schedule()[0] == 1
+    assert plan.schedule()[0] == 0
     nodes = torch.from_numpy(w.nodes).cuda()
     mat = torch.from_numpy(w.mat).cuda()
+    plan.set_schedule(1, 1)
     a, sa = plan.execute(nodes, mat)
     plan.set_schedule(0)
     b, sb = plan.execute(nodes, mat)
@@ -277,13 +278,16 @@ def test_autotune_and_cache(env, tmp_path):
     assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("name,E", [("scalar_mixed", 150), ("vector_n6", 40)])
-def test_graph_replay(env, name, E):
+@pytest.mark.parametrize("name,E,mode", [("scalar_mixed", 150, 0), ("scalar_mixed", 150, 1), ("vector_n6", 40, 0)])
+def test_graph_replay(env, name, E, mode):
     """Captured execution replayed several times, with eager work and
-    synchronizations between replays; every replay equals the eager fill."""
+    synchronizations between replays; every replay equals the eager fill
+    (mode 1: the persistent launch, whose work counter is reset inside the
+    graph)."""
     torch, W = env["torch"], env["W"]
     w = W.make(name, E=E)
     plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
+    plan.set_schedule(mode, 1)
     nodes = torch.from_numpy(w.nodes).cuda()
     mat = torch.from_numpy(w.mat).cuda()
     ref, rst = plan.execute(nodes, mat)
