@@ -102,7 +102,7 @@ def main():
                          "reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the fill is element-parallel and this build runs on a "
+        print("bench.py measures one GPU: the fill is element-parallel and is measured on a "
               "single MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
