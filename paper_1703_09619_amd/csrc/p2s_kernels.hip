@@ -426,13 +426,36 @@ __device__ void moments_valu(const ElemDesc &d, int f, const double *__restrict_
     constexpr int KS = K + 1;  // LDS row stride
     double *P1 = sm;          // [Qu*Qv][KS]   (q)
     double *P2 = sm + p2off;  // [Qu][K][KS]   (l, q)
+    double *A0 = sm + p2off;  // [Qu*Qv][Qw|1] samples, dead before P2 is written
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int QW1 = Qw | 1;   // odd row stride: the lanes of pass 1 read distinct banks
+    // stage the samples: coalesced reads, eight in flight per lane
+    {
+        constexpr int U = 8;
+        for (int x0 = tid; x0 < P; x0 += U * nt) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = x0 + u * nt;
+                v[u] = x < P ? A[x] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = x0 + u * nt;
+                if (x < P) {
+                    const int ab = x / Qw;
+                    A0[ab * QW1 + (x - ab * Qw)] = v[u];
+                }
+            }
+        }
+    }
+    __syncthreads();
     // pass 1: contract w
     for (int ab = tid; ab < Qu * Qv; ab += nt) {
         double acc[K];
 #pragma unroll
         for (int q = 0; q < K; ++q) acc[q] = 0.0;
-        const double *Ar = A + (int64_t)ab * Qw;
+        const double *Ar = A0 + ab * QW1;
         for (int c = 0; c < Qw; ++c) {
             const double x = Ar[c];
 #pragma unroll
@@ -509,16 +532,18 @@ size_t moments_smem_bytes(int maxN, int maxQw, int maxQvw)
     if ((size_t)(K * K * K) > p2) n += (size_t)(K * K * K);
     return sizeof(double) * (n > 4 * TAIL_REC ? n : 4 * TAIL_REC);
 }
-// LDS layout of k_moments_valu: P1 [Qu*Qv][K+1] followed by P2 [Qu][K][K+1].
+// LDS layout of k_moments_valu: P1 [Qu*Qv][K+1] followed by P2 [Qu][K][K+1],
+// which first holds the staged samples [Qu*Qv][Qw|1].
 static int valu_p2_offset(int maxN, int maxQuv) { return maxQuv * (2 * maxN); }
-static size_t valu_smem_bytes(int maxN, int maxQu, int maxQuv)
+static size_t valu_smem_bytes(int maxN, int maxQu, int maxQuv, int maxQw)
 {
     const int K = 2 * maxN - 1;
-    return sizeof(double) * (size_t)(valu_p2_offset(maxN, maxQuv) + maxQu * K * (K + 1));
+    const size_t p2 = (size_t)maxQu * K * (K + 1), a0 = (size_t)maxQuv * (maxQw | 1);
+    return sizeof(double) * ((size_t)valu_p2_offset(maxN, maxQuv) + (p2 > a0 ? p2 : a0));
 }
 size_t moments_lds_bytes(const MomentShape &m)
 {
-    return m.maxQ <= SPLIT_MAXQ ? valu_smem_bytes(m.maxN, m.maxQu, m.maxQuv)
+    return m.maxQ <= SPLIT_MAXQ ? valu_smem_bytes(m.maxN, m.maxQu, m.maxQuv, m.maxQw)
                                 : moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw);
 }
 
@@ -580,7 +605,7 @@ void launch_moments(int problem, const MomentShape &m, const ElemDesc *desc, int
                            moments_p2_offset(m.maxN, m.maxQvw), only, tailst);
     else if (m.maxQ <= SPLIT_MAXQ)
         hipLaunchKernelGGL(k_moments_valu, dim3((unsigned)count, F), dim3(256),
-                           valu_smem_bytes(m.maxN, m.maxQu, m.maxQuv), st, desc, e0, alpha, tab, mom,
+                           valu_smem_bytes(m.maxN, m.maxQu, m.maxQuv, m.maxQw), st, desc, e0, alpha, tab, mom,
                            valu_p2_offset(m.maxN, m.maxQuv), only);
     else
         hipLaunchKernelGGL(k_moments<false>, dim3((unsigned)count, F), dim3(256),
