@@ -39,8 +39,10 @@ struct p2s_ctx_s {
 
 struct Chunk {
     int64_t e0 = 0, count = 0;
-    // per order class inside the chunk: (N, offset into elist, count)
+    // per order class inside the chunk: (N, offset into elist, count), and
+    // the largest rules of its elements (the moment stage's LDS shape)
     std::vector<std::array<int64_t, 3>> classes;
+    std::vector<MomentShape> cshape;
     // persistent schedule: offset and count of this chunk's work items
     int64_t item0 = 0, nitem = 0;
 };
@@ -389,10 +391,23 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
         for (auto &c : plan->chunks) {
             for (int N = 2; N <= P2S_MAX_ORDER; ++N) {
                 const int64_t start = (int64_t)elist.size();
+                MomentShape cs;
+                cs.maxN = N;
                 for (int64_t e = c.e0; e < c.e0 + c.count; ++e)
-                    if (orders[e] == N) elist.push_back((int32_t)e);
+                    if (orders[e] == N) {
+                        elist.push_back((int32_t)e);
+                        const int32_t *q = quad + 3 * e;
+                        cs.maxQ = std::max({cs.maxQ, (int)q[0], (int)q[1], (int)q[2]});
+                        cs.maxQu = std::max(cs.maxQu, (int)q[0]);
+                        cs.maxQuv = std::max(cs.maxQuv, (int)(q[0] * q[1]));
+                        cs.maxQw = std::max(cs.maxQw, (int)q[2]);
+                        cs.maxQvw = std::max(cs.maxQvw, (int)(q[1] * q[2]));
+                    }
                 const int64_t cnt = (int64_t)elist.size() - start;
-                if (cnt > 0) c.classes.push_back({N, start, cnt});
+                if (cnt > 0) {
+                    c.classes.push_back({N, start, cnt});
+                    c.cshape.push_back(cs);
+                }
             }
         }
     }
@@ -502,6 +517,12 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         if (split && stop != STOP_TAILREC)
             launch_moments_split(problem, plan->d_desc, c.e0, c.count, plan->d_alpha, ctx->d_tab32,
                                  reinterpret_cast<float *>(plan->d_mom), st);
+        else if (!plan->uniform && !learned && stop != STOP_TAILREC)
+            // mixed orders: one launch per order class, each with the LDS
+            // shape of its own elements rather than of the largest order
+            for (size_t k = 0; k < c.classes.size(); ++k)
+                launch_moments(problem, c.cshape[k], plan->d_desc, c.classes[k][1], c.classes[k][2],
+                               plan->d_alpha, ctx->d_tab, plan->d_mom, nullptr, nullptr, st, plan->d_elist);
         else
             launch_moments(problem, plan->mshape, plan->d_desc, c.e0, c.count,
                            plan->d_alpha, ctx->d_tab, plan->d_mom, nullptr,

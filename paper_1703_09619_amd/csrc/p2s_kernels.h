@@ -27,10 +27,11 @@ void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t coun
                      const double *tab, double *alpha, uint32_t *status, const int32_t *only, hipStream_t st);
 // Moment stage: the matrix-core form with tail records when tailst is
 // given, else the vector-unit form when every rule has at most 16 points,
-// else the matrix-core form.
+// else the matrix-core form.  m bounds the shapes of the elements launched:
+// elements e0..e0+count-1, or elist[e0..e0+count-1] when elist is given.
 void launch_moments(int problem, const MomentShape &m, const ElemDesc *desc, int64_t e0, int64_t count,
                     const double *alpha, const double *tab, double *mom, const int32_t *only, double *tailst,
-                    hipStream_t st);
+                    hipStream_t st, const int32_t *elist = nullptr);
 int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0,
                     int64_t count, const double *tab, const double *mom, double *out, uint32_t *status,
                     double sK, double sM, hipStream_t st);

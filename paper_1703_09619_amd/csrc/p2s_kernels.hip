@@ -394,10 +394,11 @@ __global__ __launch_bounds__(256) void k_moments(const ElemDesc *__restrict__ de
                                                  const double *__restrict__ alpha,
                                                  const double *__restrict__ tab,
                                                  double *__restrict__ mom, int p2off,
-                                                 const int32_t *__restrict__ only, double *__restrict__ tailst)
+                                                 const int32_t *__restrict__ only, double *__restrict__ tailst,
+                                                 const int32_t *__restrict__ elist)
 {
     extern __shared__ double sm[];
-    const int64_t e = e0 + blockIdx.x;
+    const int64_t e = elist ? (int64_t)elist[e0 + blockIdx.x] : e0 + blockIdx.x;
     if (only && !only[e]) return;
     const ElemDesc d = desc[e];
     if (TAIL && d.Qu >= MLP_KMAX && d.Qv >= MLP_KMAX && d.Qw >= MLP_KMAX) {
@@ -500,10 +501,11 @@ __device__ void moments_valu(const ElemDesc &d, int f, const double *__restrict_
 __global__ __launch_bounds__(256) void k_moments_valu(const ElemDesc *__restrict__ desc, int64_t e0,
                                                       const double *__restrict__ alpha,
                                                       const double *__restrict__ tab, double *__restrict__ mom,
-                                                      int p2off, const int32_t *__restrict__ only)
+                                                      int p2off, const int32_t *__restrict__ only,
+                                                      const int32_t *__restrict__ elist)
 {
     extern __shared__ double sm[];
-    const int64_t e = e0 + blockIdx.x;
+    const int64_t e = elist ? (int64_t)elist[e0 + blockIdx.x] : e0 + blockIdx.x;
     if (only && !only[e]) return;
     const ElemDesc d = desc[e];
     const int f = blockIdx.y;
@@ -595,22 +597,22 @@ void launch_coupling(int problem, const ElemDesc *desc, int64_t e0, int64_t coun
 
 void launch_moments(int problem, const MomentShape &m, const ElemDesc *desc, int64_t e0, int64_t count,
                     const double *alpha, const double *tab, double *mom, const int32_t *only, double *tailst,
-                    hipStream_t st)
+                    hipStream_t st, const int32_t *elist)
 {
     if (count <= 0) return;
     const int F = num_fields(problem);
     if (tailst)
         hipLaunchKernelGGL(k_moments<true>, dim3((unsigned)count, F), dim3(256),
                            moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw), st, desc, e0, F, alpha, tab, mom,
-                           moments_p2_offset(m.maxN, m.maxQvw), only, tailst);
+                           moments_p2_offset(m.maxN, m.maxQvw), only, tailst, elist);
     else if (m.maxQ <= SPLIT_MAXQ)
         hipLaunchKernelGGL(k_moments_valu, dim3((unsigned)count, F), dim3(256),
                            valu_smem_bytes(m.maxN, m.maxQu, m.maxQuv, m.maxQw), st, desc, e0, alpha, tab, mom,
-                           valu_p2_offset(m.maxN, m.maxQuv), only);
+                           valu_p2_offset(m.maxN, m.maxQuv), only, elist);
     else
         hipLaunchKernelGGL(k_moments<false>, dim3((unsigned)count, F), dim3(256),
                            moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw), st, desc, e0, F, alpha, tab, mom,
-                           moments_p2_offset(m.maxN, m.maxQvw), only, tailst);
+                           moments_p2_offset(m.maxN, m.maxQvw), only, tailst, elist);
 }
 
 int prepare_kernels()
