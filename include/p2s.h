@@ -57,7 +57,11 @@ typedef enum {
     P2S_OK = 0,
     P2S_EINVAL = -1,   /* bad argument (null pointer, size, enum)          */
     P2S_EORDER = -2,   /* polynomial order outside [2, P2S_MAX_ORDER]       */
-    P2S_EQUAD = -3,    /* Gauss points per axis outside [1, P2S_MAX_Q]      */
+    P2S_EQUAD = -3,    /* Gauss points per axis outside [1, P2S_MAX_Q], or a
+                          rule whose moment stage exceeds the 160 KiB of LDS
+                          at the plan's largest order (order 8: up to 30
+                          points per axis on a cubic rule; order 6 and
+                          below: any allowed rule)                        */
     P2S_ENOMEM = -4,   /* device or host allocation failed (plan creation)  */
     P2S_EHIP = -5,     /* a HIP runtime call failed                         */
     P2S_ENODEV = -6,   /* no usable gfx950 device                           */

@@ -108,6 +108,22 @@ def test_vector_orders_anisotropic_rule(env, N):
     check_against_oracle(env, w)
 
 
+@pytest.mark.parametrize("problem,N,Q,E", [(0, 8, (30, 30, 30), 1), (1, 6, (32, 17, 24), 2)])
+def test_largest_rules(env, problem, N, Q, E):
+    """Rules above 16 points (the matrix-core form of the moment stage) up
+    to the largest the stage's LDS takes: 30^3 at order 8, 32 per axis at
+    order 6."""
+    w = make_small(env, problem, N, E, Q, seed=400 + N)
+    check_against_oracle(env, w)
+
+
+def test_rule_beyond_moment_lds_is_refused(env):
+    """Order 8 with 32^3 points needs 182 KB of LDS in the moment stage:
+    plan creation refuses it (no launch)."""
+    with pytest.raises(env["p2s"].P2SError):
+        env["ctx"].plan(0, 0, np.array([8], np.int32), np.array([[32, 32, 32]], np.int32))
+
+
 def test_planewave_material_and_scales(env):
     w = make_small(env, 0, 5, 4, (9, 10, 11), seed=7, material=2)
     check_against_oracle(env, w, sK=0.0, sM=1.0)
