@@ -326,12 +326,20 @@ __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const d
     for (int nt = wave; nt * 16 < n2; nt += nwave) {
         const int n = nt * 16 + r16;
         const int k = n / Qw, c = n - (n / Qw) * Qw;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int ks = 0; ks < sv; ++ks) {
+        // all LDS reads of the tile first, then the chain of matrix operations
+        double xv[MAXQ / 4];
+#pragma unroll
+        for (int ks = 0; ks < MAXQ / 4; ++ks) {
             const int b = 4 * ks + k4;
-            const double x = (b < Qv && n < n2) ? P1[k * L + b * Qw + c] : 0.0;
-            if (tv) rec[13] = fmax(rec[13], fabs(x));
-            acc = mfma64(wa[ks], x, acc);
+            xv[ks] = (ks < sv && b < Qv && n < n2) ? P1[k * L + b * Qw + c] : 0.0;
+        }
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < MAXQ / 4; ++ks) {
+            if (ks < sv) {
+                if (tv) rec[13] = fmax(rec[13], fabs(xv[ks]));
+                acc = mfma64(wa[ks], xv[ks], acc);
+            }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -354,12 +362,19 @@ __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const d
     for (int ks = 0; ks < MAXQ / 4; ++ks) wa[ks] = ks < sw ? pass_weight(tab, Qw, K, tw, r16, 4 * ks + k4) : 0.0;
     for (int nt = wave; nt * 16 < n3; nt += nwave) {
         const int n = nt * 16 + r16;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int ks = 0; ks < sw; ++ks) {
+        double xw[MAXQ / 4];
+#pragma unroll
+        for (int ks = 0; ks < MAXQ / 4; ++ks) {
             const int c = 4 * ks + k4;
-            const double x = (c < Qw && n < n3) ? P2[n * QWS + c] : 0.0;
-            if (tw) rec[14] = fmax(rec[14], fabs(x));
-            acc = mfma64(wa[ks], x, acc);
+            xw[ks] = (ks < sw && c < Qw && n < n3) ? P2[n * QWS + c] : 0.0;
+        }
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < MAXQ / 4; ++ks) {
+            if (ks < sw) {
+                if (tw) rec[14] = fmax(rec[14], fabs(xw[ks]));
+                acc = mfma64(wa[ks], xw[ks], acc);
+            }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
