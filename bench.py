@@ -6,8 +6,12 @@ of the whole batch, inputs resident in HBM.  Prints ONE JSON line.
 
 Default workload (the headline): vector curl-curl + mass, N=6 (540 dofs),
 4096 curved triquadratic hexahedra, 12^3 Gauss points, rotated anisotropic
-permittivity.  The CPU baseline is the FP64 oracle (direct quadrature) on a
-bounded sample of the same elements, run on the host cores.
+permittivity.  The default run also measures the other workloads (scalar
+N=4, mixed orders, vector N=8 in FP64 and split-FP32, learned order) as
+compact entries under "configs", each with its rate, the roofline fraction
+of its contraction stage and its error against the oracle on a sample.  The
+CPU baseline is the FP64 oracle (direct quadrature), built for the host CPU,
+on a bounded sample of the headline elements.
 """
 from __future__ import annotations
 
@@ -15,6 +19,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -36,17 +41,35 @@ WORKLOADS = {
                         "|k| log-uniform in [0.5,16] pi, node noise U[0,0.3]; Gauss rule per axis chosen by the "
                         "learned order (full rule 24^3, tail check with fallback)",
 }
-CPU_SAMPLE = {"vector_n6": 24, "scalar_n4": 64, "scalar_mixed": 40, "vector_n8": 4, "scalar_planewave": 6}
+# CPU baseline: elements of the headline sample on all allotted threads,
+# and on one thread
+CPU_SAMPLE = {"vector_n6": 32, "scalar_n4": 64, "scalar_mixed": 40, "vector_n8": 4, "scalar_planewave": 6}
+CPU_SAMPLE_1T = {"vector_n6": 6, "scalar_n4": 16, "scalar_mixed": 10, "vector_n8": 1, "scalar_planewave": 2}
+
+
+def num_dofs(problem: int, N: int) -> int:
+    return N ** 3 if problem == 0 else 3 * (N - 1) * N * N
 
 
 def contract_bytes_per_element(problem: int, N: int, moment_bytes: int = 8) -> int:
     """Algorithmic HBM bytes of the contraction kernel per element: the
     dense FP64 output block written once plus the moment tensors read once
     (FP64, or FP32 in the split form)."""
-    nd = N ** 3 if problem == 0 else 3 * (N - 1) * N * N
+    nd = num_dofs(problem, N)
     F = 7 if problem == 0 else 12
     K = 2 * N - 1
     return 8 * nd * nd + moment_bytes * F * K ** 3
+
+
+def direct_flops_per_element(problem: int, N: int, Q) -> int:
+    """Algorithmic FP64 flops of direct quadrature of eq. (2) per element:
+    the upper triangle of the (symmetric) matrix, each entry a sum over the
+    Qu*Qv*Qw points of the coupling-term products (scalar: 9 stiffness + 1
+    mass; vector: 4 curl + 1 mass per entry), one multiply-add (2 flops)
+    each."""
+    nd = num_dofs(problem, N)
+    terms = 10 if problem == 0 else 5
+    return 2 * (nd * (nd + 1) // 2) * int(np.prod(Q)) * terms
 
 
 TRAFFIC_PROFILES = {("vector_n6", "fp64"): "profiles/k_contract_vector_n6.md"}
@@ -77,11 +100,192 @@ def measured_traffic(workload: str, precision: str):
 
 
 def cpu_threads() -> int:
+    """Threads the CPU baseline may use: the CPUs this process may run on,
+    capped by OMP_NUM_THREADS when the host sets it (the share of the host
+    allotted to one GPU's job)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def contraction_kernel_name(w, split, schedule):
+    uniform = len(set(w.orders.tolist())) == 1
+    if split:
+        return "k_contract_split<%d,I,J> (blocks J >= I)" % w.problem, 6 if w.problem else 1
+    if not uniform and schedule and schedule["mode"] == "persistent":
+        return "k_contract_persistent_scalar", 1
+    if not uniform:
+        return "k_contract<0,N,0,0> (one launch per order N)", len(set(w.orders.tolist()))
+    return "k_contract<%d,%d,I,J> (blocks J >= I)" % (w.problem, int(w.orders[0])), 6 if w.problem else 1
+
+
+def timed_fill(torch, p2s, ctx, w, steps, warmup, split=False, learned=None, out=None):
+    """Plan + warm-up + `steps` timed executions of workload w.  Returns
+    (info, plan, out, status): info holds ms per step, the stage times (HIP
+    events on the launch stream) and the contraction stage's roofline."""
+    dev = torch.device("cuda", 0)
+    plan = ctx.plan(w.problem, w.material, w.orders, w.quad, precision=p2s.SPLIT_FP32 if split else p2s.FP64)
+    if learned is not None:
+        plan.set_learned(True, learned["p_cover"], learned["theta"], learned.get("k_direct", p2s.KMAX + 1))
+    nodes = torch.from_numpy(w.nodes).to(dev)
+    mat = torch.from_numpy(w.mat).to(dev)
+    if out is None:
+        out = torch.empty(int(plan.offsets[-1]), dtype=torch.float64, device=dev)
+    status = torch.empty(w.E, dtype=torch.int32, device=dev)
+    schedule = None
+    if len(set(w.orders.tolist())) > 1 and not split:
+        # mixed orders: the schedule autotuner picks per-order-class launches
+        # or the persistent launch (outside the timed region)
+        plan.autotune(nodes, mat, out, status)
+        mode, wpc = plan.schedule()
+        schedule = {"mode": "per_order_class" if mode == 0 else "persistent", "wgs_per_cu": wpc,
+                    "chosen_by": "p2s_plan_autotune"}
+    for _ in range(warmup):
+        plan.execute(nodes, mat, out, status)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute(nodes, mat, out, status)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = plan.profile_read()
+    plan.profile(False)
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    c_ms, c_segments = stages["contraction"]
+    if len(set(w.orders.tolist())) > 1:
+        alg_bytes = sum(contract_bytes_per_element(w.problem, int(n)) for n in w.orders)
+    else:
+        alg_bytes = w.E * contract_bytes_per_element(w.problem, int(w.orders[0]), 4 if split else 8)
+    stage_ms = c_ms / steps
+    achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
+    kname, per_chunk = contraction_kernel_name(w, split, schedule)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": kname, "unit_of_work": "one contraction stage over the batch",
+                "algorithmic_bytes": alg_bytes, "stage_ms": round(stage_ms, 4),
+                "launches_per_step": (c_segments // steps) * per_chunk}
+    info = {"ms_per_step": ms_per_step, "value": w.E / (ms_per_step * 1e-3), "roofline": roofline,
+            "stages_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items()},
+            "schedule": schedule, "nodes": nodes, "mat": mat}
+    return info, plan, out, status
+
+
+def oracle_errors(oracle, W, w, out, offsets, idx, nthreads=0, native=False):
+    """Per-element relative Frobenius error of the GPU blocks of elements
+    idx against the oracle's direct quadrature."""
+    sub = W.subset(w, np.asarray(idx))
+    ref, roff, _ = oracle.fill(sub.problem, sub.material, sub.nodes, sub.mat, sub.orders, sub.quad,
+                               nthreads=nthreads, native=native)
+    errs = []
+    for i, e in enumerate(idx):
+        g = out[int(offsets[e]):int(offsets[e + 1])].cpu().numpy()
+        r = ref[roff[i]:roff[i + 1]]
+        errs.append(float(np.linalg.norm(g - r) / np.linalg.norm(r)))
+    return errs
+
+
+def compact_configs(torch, p2s, ctx, W, oracle, steps, warmup, log):
+    """The other workloads, each as a compact entry measured in this run."""
+    res = {}
+    # scalar N=4, 64 elements (launch-bound), every element against the oracle
+    w = W.make("scalar_n4")
+    info, plan, out, st = timed_fill(torch, p2s, ctx, w, steps, warmup)
+    errs = oracle_errors(oracle, W, w, out, plan.offsets, list(range(w.E)))
+    res["scalar_n4"] = {"elements": w.E, "value": round(info["value"], 1), "unit": "element matrices/s",
+                        "ms_per_step": round(info["ms_per_step"], 4),
+                        "roofline_frac": info["roofline"]["frac"], "bound": "hbm (launch-bound at 64 elements)",
+                        "max_rel_err_vs_oracle": max(errs), "oracle_elements": len(errs),
+                        "status_nonzero": int((st.cpu().numpy() != 0).sum())}
+    log("scalar_n4 done")
+    del plan, out
+    # mixed orders, autotuned schedule; one sampled element per order class
+    w = W.make("scalar_mixed")
+    info, plan, out, st = timed_fill(torch, p2s, ctx, w, steps, warmup)
+    rng = np.random.default_rng(7)
+    pick = sorted(int(rng.choice(np.nonzero(w.orders == n)[0])) for n in range(2, 9))
+    errs = oracle_errors(oracle, W, w, out, plan.offsets, pick)
+    res["scalar_mixed"] = {"elements": w.E, "value": round(info["value"], 1), "unit": "element matrices/s",
+                           "ms_per_step": round(info["ms_per_step"], 4), "roofline_frac": info["roofline"]["frac"],
+                           "bound": "hbm", "schedule": info["schedule"],
+                           "stages_ms_per_step": info["stages_ms_per_step"],
+                           "max_rel_err_vs_oracle": max(errs), "oracle_elements": len(errs),
+                           "status_nonzero": int((st.cpu().numpy() != 0).sum())}
+    log("scalar_mixed done")
+    del plan, out
+    torch.cuda.empty_cache()
+    # vector N=8, FP64 and split-FP32 (one output buffer for both)
+    w = W.make("vector_n8")
+    info, plan, out, st = timed_fill(torch, p2s, ctx, w, max(3, steps // 2), 1)
+    pick = [0]
+    sub = W.subset(w, pick)
+    ref, roff, _ = oracle.fill(sub.problem, sub.material, sub.nodes, sub.mat, sub.orders, sub.quad)
+    e64 = float(np.linalg.norm(out[:int(roff[1])].cpu().numpy() - ref) / np.linalg.norm(ref))
+    n64 = 64
+    off64 = torch.from_numpy(plan.offsets[:n64 + 1]).cuda()
+    keep64 = out[:int(plan.offsets[n64])].clone()
+    res["vector_n8_fp64"] = {"elements": w.E, "value": round(info["value"], 1), "unit": "element matrices/s",
+                             "ms_per_step": round(info["ms_per_step"], 4), "roofline_frac": info["roofline"]["frac"],
+                             "bound": "hbm", "stages_ms_per_step": info["stages_ms_per_step"],
+                             "max_rel_err_vs_oracle": e64, "oracle_elements": 1,
+                             "status_nonzero": int((st.cpu().numpy() != 0).sum())}
+    del plan
+    log("vector_n8 fp64 done")
+    info, plan, out, st = timed_fill(torch, p2s, ctx, w, max(3, steps // 2), 1, split=True, out=out)
+    es = float(np.linalg.norm(out[:int(roff[1])].cpu().numpy() - ref) / np.linalg.norm(ref))
+    e_vs64 = ctx.rel_error(out[:int(plan.offsets[n64])], keep64, offsets=off64).cpu().numpy()
+    res["vector_n8_split_fp32"] = {
+        "elements": w.E, "value": round(info["value"], 1), "unit": "element matrices/s",
+        "ms_per_step": round(info["ms_per_step"], 4), "roofline_frac": info["roofline"]["frac"], "bound": "hbm",
+        "stages_ms_per_step": info["stages_ms_per_step"], "max_rel_err_vs_oracle": es, "oracle_elements": 1,
+        "max_rel_err_vs_fp64_gpu": float(e_vs64.max()), "fp64_gpu_elements": n64,
+        "speedup_vs_fp64": round(res["vector_n8_fp64"]["ms_per_step"] / info["ms_per_step"], 3)}
+    del plan, out, keep64
+    torch.cuda.empty_cache()
+    log("vector_n8 split done")
+    # learned order against the full rule on the same 50000 elements
+    from paper_1703_09619_amd import learned_k
+    meta = json.load(open(os.path.splitext(learned_k.DEFAULT_MODEL)[0] + ".json"))
+    ctx.mlp_init(0, 1)
+    ctx.mlp_load(learned_k.DEFAULT_MODEL)
+    w = W.make("scalar_planewave")
+    info, plan, out, st = timed_fill(torch, p2s, ctx, w, steps, warmup, learned=meta)
+    rules = plan.rules()
+    stn = st.cpu().numpy()
+    finfo, fplan, ref, _ = timed_fill(torch, p2s, ctx, w, steps, warmup)
+    off = torch.from_numpy(plan.offsets).cuda()
+    err = ctx.rel_error(out, ref, offsets=off).cpu().numpy()
+    pick = [0, w.E - 1]
+    eo = oracle_errors(oracle, W, w, out, plan.offsets, pick)
+    res["scalar_planewave_learned"] = {
+        "elements": w.E, "value": round(info["value"], 1), "unit": "element matrices/s",
+        "ms_per_step": round(info["ms_per_step"], 4), "roofline_frac": info["roofline"]["frac"], "bound": "hbm",
+        "stages_ms_per_step": info["stages_ms_per_step"],
+        "full_rule_value": round(finfo["value"], 1), "speedup_vs_full_rule": round(finfo["ms_per_step"] /
+                                                                                  info["ms_per_step"], 3),
+        "max_rel_err_vs_full_rule": float(err.max()), "elements_over_1e-8": int((err > 1e-8).sum()),
+        "max_rel_err_vs_oracle_24": max(eo), "oracle_elements": len(eo),
+        "fallback_rate": float(((stn & 4) != 0).mean()), "mean_points": float(np.prod(rules, 1).mean()),
+        "model": {k: meta[k] for k in ("p_cover", "k_direct", "theta", "tol") if k in meta}}
+    log("scalar_planewave done")
+    del plan, fplan, out, ref
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -91,6 +295,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="vector_n6", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--configs", default="auto", choices=["auto", "all", "none"],
+                    help="measure the other workloads as compact entries (auto: with the default headline)")
     ap.add_argument("--direct-elements", type=int, default=64,
                     help="elements of the same workload filled by the GPU direct-quadrature baseline "
                          "(0 = skip)")
@@ -106,6 +312,9 @@ def main():
               "single MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    def log(msg):
+        print("[bench] " + msg, file=sys.stderr, flush=True)
+
     import torch
     import paper_1703_09619_amd as p2s
     from paper_1703_09619_amd import workloads as W
@@ -114,20 +323,12 @@ def main():
     dev = torch.device("cuda", 0)
     ctx = p2s.Context(0)
     split = args.precision == "split_fp32"
-    plan = ctx.plan(w.problem, w.material, w.orders, w.quad, precision=p2s.SPLIT_FP32 if split else p2s.FP64)
     learned = None
     if args.workload == "scalar_planewave":
         from paper_1703_09619_amd import learned_k
-        meta = json.load(open(os.path.splitext(learned_k.DEFAULT_MODEL)[0] + ".json"))
+        learned = json.load(open(os.path.splitext(learned_k.DEFAULT_MODEL)[0] + ".json"))
         ctx.mlp_init(0, 1)
         ctx.mlp_load(learned_k.DEFAULT_MODEL)
-        plan.set_learned(True, meta["p_cover"], meta["theta"], meta.get("k_direct", p2s.KMAX + 1))
-        learned = meta
-    nodes = torch.from_numpy(w.nodes).to(dev)
-    mat = torch.from_numpy(w.mat).to(dev)
-    out = torch.empty(int(plan.offsets[-1]), dtype=torch.float64, device=dev)
-    status = torch.empty(w.E, dtype=torch.int32, device=dev)
-    torch.cuda.synchronize()
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
         dst = torch.empty_like(src)
@@ -136,63 +337,21 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    schedule = None
-    if len(set(w.orders.tolist())) > 1 and not split:
-        # mixed orders: the schedule autotuner picks per-order-class launches
-        # or the persistent launch (outside the timed region)
-        plan.autotune(nodes, mat, out, status)
-        mode, wpc = plan.schedule()
-        schedule = {"mode": "per_order_class" if mode == 0 else "persistent", "wgs_per_cu": wpc,
-                    "chosen_by": "p2s_plan_autotune"}
-
-    for _ in range(args.warmup):
-        plan.execute(nodes, mat, out, status)
-    torch.cuda.synchronize()
-    plan.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.execute(nodes, mat, out, status)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stages = plan.profile_read()
-    plan.profile(False)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = w.E / (ms_per_step * 1e-3)
+    info, plan, out, status = timed_fill(torch, p2s, ctx, w, args.steps, args.warmup, split=split, learned=learned)
+    nodes, mat = info["nodes"], info["mat"]
+    ms_per_step = info["ms_per_step"]
+    value = info["value"]
     st = status.cpu().numpy()
-
-    # dominant kernel: the contraction stage (HIP events on the launch stream
-    # around the stage's launches: one kernel per component block, per order
-    # class for mixed orders, or one persistent kernel)
-    c_ms, c_segments = stages["contraction"]
-    if w.problem == 0 and len(set(w.orders.tolist())) > 1:
-        alg_bytes = sum(contract_bytes_per_element(0, int(n)) for n in w.orders)
-    else:
-        alg_bytes = w.E * contract_bytes_per_element(w.problem, int(w.orders[0]), 4 if split else 8)
-    stage_ms = c_ms / args.steps
-    achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
-    n_uniform = len(set(w.orders.tolist())) == 1
-    if split:
-        kname, per_chunk = "k_contract_split<%d,I,J> (blocks J >= I)" % w.problem, 6 if w.problem else 1
-    elif not n_uniform and schedule["mode"] == "persistent":
-        kname, per_chunk = "k_contract_persistent_scalar", 1
-    elif not n_uniform:
-        kname, per_chunk = "k_contract<0,N,0,0> (one launch per order N)", len(set(w.orders.tolist()))
-    else:
-        kname = "k_contract<%d,%d,I,J> (blocks J >= I)" % (w.problem, int(w.orders[0]))
-        per_chunk = 6 if w.problem else 1
+    roofline = info["roofline"]
     traffic = measured_traffic(args.workload, args.precision)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else round(traffic),
-                "kernel": kname, "unit_of_work": "one contraction stage over the batch",
-                "algorithmic_bytes": alg_bytes, "stage_ms": round(stage_ms, 4),
-                "launches_per_step": (c_segments // args.steps) * per_chunk}
+    roofline["traffic"] = None if traffic is None else round(traffic)
+    log("headline %s: %.1f element matrices/s" % (args.workload, value))
 
+    learned_info = None
     if learned is not None:
         # the same plan without the network (full rule on every axis)
         ref = torch.empty_like(out)
         rst = torch.empty_like(status)
-        stn = st
         rules = plan.rules()
         plan.set_learned(False)
         plan.execute(nodes, mat, ref, rst)
@@ -203,10 +362,11 @@ def main():
         torch.cuda.synchronize()
         f1 = time.perf_counter()
         err = ctx.rel_error(out, ref, offsets=torch.from_numpy(plan.offsets).to(dev)).cpu().numpy()
-        learned.update(full_rule_elements_per_s=round(w.E / ((f1 - f0) / args.steps), 1),
-                       speedup=round(((f1 - f0) / args.steps) / (ms_per_step * 1e-3), 3),
-                       max_rel_err_vs_full_rule=float(err.max()),
-                       fallback_rate=float(((stn & 4) != 0).mean()), mean_points=float(np.prod(rules, 1).mean()))
+        learned_info = dict(learned)
+        learned_info.update(full_rule_elements_per_s=round(w.E / ((f1 - f0) / args.steps), 1),
+                            speedup=round(((f1 - f0) / args.steps) / (ms_per_step * 1e-3), 3),
+                            max_rel_err_vs_full_rule=float(err.max()),
+                            fallback_rate=float(((st & 4) != 0).mean()), mean_points=float(np.prod(rules, 1).mean()))
         del ref
 
     precision = None
@@ -232,13 +392,13 @@ def main():
         "data": "synthetic (seeded curved triquadratic hexahedra and analytic materials)",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "elements": w.E,
                    "orders": sorted(set(int(n) for n in w.orders)), "gauss_points": w.quad[0].tolist(),
-                   **({"schedule": schedule} if schedule else {})},
+                   **({"schedule": info["schedule"]} if info["schedule"] else {})},
         "roofline": roofline,
-        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
+        "stages_ms_per_step": info["stages_ms_per_step"],
         "status_nonzero": int((st != 0).sum()),
     }
-    if learned is not None:
-        result["learned_order"] = learned
+    if learned_info is not None:
+        result["learned_order"] = learned_info
 
     if args.direct_elements > 0 and len(set(w.orders.tolist())) == 1:
         # the method the paper compares against, on the GPU: direct quadrature
@@ -251,42 +411,52 @@ def main():
         dst = torch.empty(sub.E, dtype=torch.int32, device=dev)
         dplan.execute(dn, dm, dout, dst)
         torch.cuda.synchronize()
-        d0 = time.perf_counter()
         reps = 3
+        dplan.profile(True)
+        d0 = time.perf_counter()
         for _ in range(reps):
             dplan.execute(dn, dm, dout, dst)
         torch.cuda.synchronize()
         d1 = time.perf_counter()
+        dst_ms = dplan.profile_read()["other"][0] / reps
         ref = out[:int(dplan.offsets[-1])]
         derr = float(((dout - ref).norm() / ref.norm()).item())
+        flops = sub.E * direct_flops_per_element(w.problem, int(w.orders[0]), w.quad[0])
+        tf = flops / (dst_ms * 1e-3) / 1e12
         result["gpu_direct_quadrature"] = {
             "value": round(sub.E * reps / (d1 - d0), 1), "unit": "element matrices/s", "elements": sub.E,
-            "rel_frobenius_diff_vs_p2s": derr}
+            "rel_frobenius_diff_vs_p2s": derr,
+            "roofline": {"bound": "fp64", "kernel": "k_direct<%d>" % w.problem, "achieved": round(tf, 2),
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                         "algorithmic_flops": flops, "kernel_ms": round(dst_ms, 4)}}
         del dout
+        log("direct baseline done")
 
     if not args.no_cpu_baseline:
         import oracle
-        oracle.build(force=False)
+        tmpd = tempfile.mkdtemp(prefix="p2s_oracle_")
+        oracle.use_native(tmpd)
         n = min(CPU_SAMPLE[args.workload], w.E)
         idx = np.random.default_rng(7).choice(w.E, size=n, replace=False)
         idx.sort()
-        sub = W.subset(w, idx)
         cores = cpu_threads()
         c0 = time.perf_counter()
-        ref, roff, _ = oracle.fill(sub.problem, sub.material, sub.nodes, sub.mat, sub.orders, sub.quad,
-                                   nthreads=cores)
+        errs = oracle_errors(oracle, W, w, out, plan.offsets, idx, nthreads=cores, native=True)
         c1 = time.perf_counter()
-        errs = []
-        off = plan.offsets
-        for i, e in enumerate(idx):
-            g = out[int(off[e]):int(off[e + 1])].cpu().numpy()
-            r = ref[roff[i]:roff[i + 1]]
-            errs.append(float(np.linalg.norm(g - r) / np.linalg.norm(r)))
-        result["cpu_baseline"] = {"value": round(n / (c1 - c0), 3), "unit": "element matrices/s",
-                                  "cores": cores, "kind": "oracle",
-                                  "sample": "%d seeded elements of the same workload, direct quadrature, "
-                                            "FP64, OpenMP over elements" % n}
+        n1 = min(CPU_SAMPLE_1T[args.workload], n)
+        sub1 = W.subset(w, idx[:n1])
+        s0 = time.perf_counter()
+        oracle.fill(sub1.problem, sub1.material, sub1.nodes, sub1.mat, sub1.orders, sub1.quad, nthreads=1,
+                    native=True)
+        s1 = time.perf_counter()
+        result["cpu_baseline"] = {
+            "value": round(n / (c1 - c0), 3), "unit": "element matrices/s", "cores": cores, "kind": "oracle",
+            "sample": "%d seeded elements of the same workload (GPU blocks compared with them), direct "
+                      "quadrature, FP64, gcc -O3 -march=native, OpenMP over elements" % n,
+            "single_core_value": round(n1 / (s1 - s0), 3), "single_core_sample": "%d of those elements" % n1,
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
         result["max_rel_err_vs_oracle"] = max(errs)
+        log("cpu baseline done")
     if precision is not None:
         del plan
         p64 = ctx.plan(w.problem, w.material, w.orders, w.quad)
@@ -300,6 +470,14 @@ def main():
         precision["fp64_elements_per_s"] = round(w.E * args.steps / (f1 - f0), 1)
         precision["split_speedup_vs_fp64"] = round((f1 - f0) / args.steps / (ms_per_step * 1e-3), 3)
         result["precision"] = precision
+
+    run_configs = args.configs == "all" or (args.configs == "auto" and args.workload == "vector_n6" and not split)
+    if run_configs:
+        import oracle
+        del out, status
+        plan = None
+        torch.cuda.empty_cache()
+        result["configs"] = compact_configs(torch, p2s, ctx, W, oracle, args.steps, args.warmup, log)
     print(json.dumps(result), flush=True)
 
 

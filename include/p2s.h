@@ -114,7 +114,6 @@ typedef struct {
 #define P2S_STATUS_DETJ 1u      /* det J <= 0 at some Gauss point          */
 #define P2S_STATUS_NONFINITE 2u /* non-finite value in the element matrix */
 #define P2S_STATUS_FALLBACK 4u  /* learned order rejected, refilled at max */
-#define P2S_STATUS_TAIL 8u      /* reserved (not set)                      */
 
 /* Create a context on HIP device `device`: checks that it is gfx950,
  * builds the FP64 tables (Gauss rules up to P2S_MAX_Q points, Legendre
@@ -269,9 +268,18 @@ int p2s_plan_tail_values(p2s_plan plan, double *tau);
 int p2s_rel_error(p2s_ctx ctx, int64_t E, int64_t len, const int64_t *offsets, const double *a, const double *b,
                   double *err, void *stream);
 
-/* One-shot fill: plan create + execute + destroy (the plan is destroyed
- * after the stream has finished the work, so this call synchronizes the
- * stream).  Arguments as above. */
+/* The fill of eq. (2) by the product-to-sum method of Section II (eqs.
+ * (3)-(4)) in one call, arguments as for p2s_plan_create and
+ * p2s_plan_execute: terms [host], orders [host][E], quad [host][E][3],
+ * nodes/material/out/status [device] as in p2s_plan_execute, out laid out
+ * by p2s_layout.  The context keeps the plans of the last 8 batch shapes
+ * (terms, E, orders, quad compared exactly): the first call of a shape
+ * creates its plan (allocates device memory and uploads descriptors, which
+ * may block), every later call of that shape only enqueues the fill on
+ * `stream` and returns, allocating nothing.  A ninth shape evicts the least
+ * recently used plan (its memory is freed once the device has finished the
+ * work queued on it).  Returns the plan-creation or launch error; numerical
+ * conditions go to status. */
 int p2s_fill_element_matrices(p2s_ctx ctx, const p2s_terms *terms, int64_t E,
                               const double *nodes, const double *material,
                               const int32_t *orders, const int32_t *quad,

@@ -26,45 +26,72 @@ MAT_SINCOSEXP, MAT_ROTDIAG, MAT_PLANEWAVE, ALPHA_SAMPLED = 0, 1, 2, 3
 STATUS_DETJ, STATUS_NONFINITE = 1, 2
 
 _lib = None
+_native = None
+
+# IEEE FP64 without value-changing optimizations: no fast-math, no FMA
+# contraction (the oracle's sums round exactly as written)
+_FP_FLAGS = ["-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared"]
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c with gcc into liboracle.so (FP64, no fast-math)."""
+    """Compile oracle.c with gcc into liboracle.so (portable -O2 build, the
+    one the tests load; it travels with the tree to other hosts)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
-               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", "-O2"] + _FP_FLAGS + ["-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
 
 
-def _load():
+def build_native(directory: str) -> str:
+    """Compile oracle.c with -O3 -march=native for the host it runs on, into
+    `directory` (the timed CPU baseline; the same source and FP64 rules as
+    the test build, vectorized for this CPU)."""
+    path = os.path.join(directory, "liboracle_native.so")
+    subprocess.check_call(["gcc", "-O3", "-march=native"] + _FP_FLAGS + ["-o", path, _SRC, "-lm"])
+    return path
+
+
+def use_native(directory: str) -> None:
+    """Make fill() run the -O3 -march=native build from build_native()."""
+    global _native
+    _native = _bind(ctypes.CDLL(build_native(directory)))
+
+
+def _load(native: bool = False):
     global _lib
+    if native:
+        if _native is None:
+            raise RuntimeError("use_native() has not been called")
+        return _native
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
-        d, i, i64, vp = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
-        lib.oracle_gauss_legendre.argtypes = [i, vp, vp]
-        lib.oracle_gauss_legendre.restype = i
-        for f in ("oracle_phi", "oracle_dphi", "oracle_psi"):
-            getattr(lib, f).argtypes = [i, d]
-            getattr(lib, f).restype = d
-        lib.oracle_map.argtypes = [vp, d, d, d, vp, vp]
-        lib.oracle_map.restype = None
-        lib.oracle_eps.argtypes = [i, vp, vp, vp]
-        lib.oracle_eps.restype = None
-        lib.oracle_coupling.argtypes = [i, i, vp, vp, i, i, i, vp]
-        lib.oracle_coupling.restype = d
-        lib.oracle_fill.argtypes = [i, i, i64, vp, vp, vp, vp, vp, d, d, vp, vp, i]
-        lib.oracle_fill.restype = i
-        lib.oracle_moments.argtypes = [i, i, vp, vp, i, i, i, i, vp]
-        lib.oracle_moments.restype = i
-        lib.oracle_num_dofs.argtypes = [i, i]
-        lib.oracle_num_dofs.restype = i64
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
+
+
+def _bind(lib):
+    d, i, i64, vp = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+    lib.oracle_gauss_legendre.argtypes = [i, vp, vp]
+    lib.oracle_gauss_legendre.restype = i
+    for f in ("oracle_phi", "oracle_dphi", "oracle_psi"):
+        getattr(lib, f).argtypes = [i, d]
+        getattr(lib, f).restype = d
+    lib.oracle_map.argtypes = [vp, d, d, d, vp, vp]
+    lib.oracle_map.restype = None
+    lib.oracle_eps.argtypes = [i, vp, vp, vp]
+    lib.oracle_eps.restype = None
+    lib.oracle_coupling.argtypes = [i, i, vp, vp, i, i, i, vp]
+    lib.oracle_coupling.restype = d
+    lib.oracle_fill.argtypes = [i, i, i64, vp, vp, vp, vp, vp, d, d, vp, vp, i]
+    lib.oracle_fill.restype = i
+    lib.oracle_moments.argtypes = [i, i, vp, vp, i, i, i, i, vp]
+    lib.oracle_moments.restype = i
+    lib.oracle_num_dofs.argtypes = [i, i]
+    lib.oracle_num_dofs.restype = i64
+    return lib
 
 
 def _ptr(a: np.ndarray):
@@ -148,8 +175,9 @@ def layout(problem: int, orders) -> np.ndarray:
     return off
 
 
-def fill(problem, material, nodes, mat, orders, quad, s_K=1.0, s_M=1.0, nthreads=0):
-    """Element matrices by direct quadrature.
+def fill(problem, material, nodes, mat, orders, quad, s_K=1.0, s_M=1.0, nthreads=0, native=False):
+    """Element matrices by direct quadrature (nthreads OpenMP threads over
+    elements, 0 = OpenMP's default; native: the build_native() library).
 
     Returns (out, offsets, status): out is the concatenation of the dense
     row-major FP64 blocks, offsets[E+1] their starts.
@@ -162,7 +190,7 @@ def fill(problem, material, nodes, mat, orders, quad, s_K=1.0, s_M=1.0, nthreads
     off = layout(problem, orders)
     out = np.zeros(int(off[-1]))
     status = np.zeros(E, dtype=np.uint32)
-    rc = _load().oracle_fill(problem, material, E, _ptr(nodes), _ptr(mat), _ptr(orders),
+    rc = _load(native).oracle_fill(problem, material, E, _ptr(nodes), _ptr(mat), _ptr(orders),
                              _ptr(quad), _ptr(off), float(s_K), float(s_M),
                              _ptr(out), _ptr(status), int(nthreads))
     if rc != 0:

@@ -24,7 +24,7 @@ MAT_SINCOSEXP, MAT_ROTDIAG, MAT_PLANEWAVE, ALPHA_SAMPLED = 0, 1, 2, 3
 FP64, SPLIT_FP32 = 0, 1
 METHOD_P2S, METHOD_DIRECT = 0, 1
 FAM_PHI, FAM_DPHI, FAM_PSI = 0, 1, 2
-STATUS_DETJ, STATUS_NONFINITE, STATUS_FALLBACK, STATUS_TAIL = 1, 2, 4, 8
+STATUS_DETJ, STATUS_NONFINITE, STATUS_FALLBACK = 1, 2, 4
 MAX_ORDER, MAX_Q = 8, 32
 
 # every symbol the C ABI exports (include/p2s.h)
@@ -186,15 +186,6 @@ class Context:
         if rc != 0:
             raise P2SError("%s failed (%d): %s" % (what, rc, self.error()))
 
-    def tail_records(self, nodes, material, stream=None):
-        """[E][F][16] tail records of the moment stage at the plan's rules."""
-        import torch
-        F = 7 if self.terms.problem == SCALAR else 12
-        r = torch.zeros(self.E * F * 16, dtype=torch.float64, device=torch.device("cuda", self.ctx.device))
-        rc = load().p2s_plan_tail_records(self._h, _dev_ptr(nodes), _dev_ptr(material), _dev_ptr(r), _stream(stream))
-        self.ctx.check(rc, "p2s_plan_tail_records")
-        return r.view(self.E, F, 16)
-
     def close(self):
         if getattr(self, "_h", None):
             load().p2s_destroy(self._h)
@@ -269,6 +260,27 @@ class Context:
         self.check(load().p2s_rel_error(self._h, E, block, _dev_ptr(offsets), _dev_ptr(a), _dev_ptr(b),
                                         _dev_ptr(err), _stream(stream)), "p2s_rel_error")
         return err
+
+    def fill_element_matrices(self, problem, material_kind, nodes, material, orders, quad, out=None,
+                              status=None, precision=FP64, method=METHOD_P2S, stiff_scale=1.0, mass_scale=1.0,
+                              stream=None):
+        """p2s_fill_element_matrices: the one-shot fill (plans cached per
+        batch shape in the context).  Returns (out, status)."""
+        import torch
+        t = terms(problem, material_kind, precision, method, stiff_scale, mass_scale)
+        orders = np.ascontiguousarray(orders, dtype=np.int32)
+        quad = np.ascontiguousarray(quad, dtype=np.int32).reshape(-1, 3)
+        E = len(orders)
+        dev = torch.device("cuda", self.device)
+        if out is None:
+            out = torch.empty(int(layout(problem, orders)[-1]) if E else 0, dtype=torch.float64, device=dev)
+        if status is None:
+            status = torch.empty(E, dtype=torch.int32, device=dev)
+        rc = load().p2s_fill_element_matrices(self._h, ctypes.byref(t), E, _dev_ptr(nodes), _dev_ptr(material),
+                                              _np_ptr(orders), _np_ptr(quad), _dev_ptr(out), _dev_ptr(status),
+                                              _stream(stream))
+        self.check(rc, "p2s_fill_element_matrices")
+        return out, status
 
     def plan(self, problem, material, orders, quad, precision=FP64, method=METHOD_P2S,
              stiff_scale=1.0, mass_scale=1.0) -> "Plan":

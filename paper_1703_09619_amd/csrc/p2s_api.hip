@@ -35,7 +35,10 @@ struct p2s_ctx_s {
     int64_t mlp_bmax = 0;
     float *d_h1 = nullptr, *d_h2 = nullptr, *d_z = nullptr, *d_dz = nullptr, *d_dh2 = nullptr, *d_dh1 = nullptr,
           *d_lossb = nullptr;
+    // plans of p2s_fill_element_matrices, least recently used first
+    std::vector<p2s_plan> fill_cache;
 };
+constexpr size_t FILL_CACHE_PLANS = 8;
 
 struct Chunk {
     int64_t e0 = 0, count = 0;
@@ -220,6 +223,8 @@ void p2s_destroy(p2s_ctx ctx)
 {
     if (!ctx) return;
     hipSetDevice(ctx->device);
+    for (p2s_plan p : ctx->fill_cache) p2s_plan_destroy(p);
+    ctx->fill_cache.clear();
     if (ctx->d_tab) hipFree(ctx->d_tab);
     if (ctx->d_tab32) hipFree(ctx->d_tab32);
     for (float *p : {ctx->d_mlp, ctx->d_grad, ctx->d_adam_m, ctx->d_adam_v, ctx->d_h1, ctx->d_h2, ctx->d_z,
@@ -644,17 +649,46 @@ int p2s_plan_tail_records(p2s_plan plan, const double *nodes, const double *mate
                     records);
 }
 
+// Plans of the one-shot entry point, cached per batch shape in the context:
+// the first call of a shape creates the plan (allocates, uploads its
+// descriptors), later calls of the same shape reuse it and only enqueue.
+static bool same_shape(p2s_plan p, const p2s_terms *t, int64_t E, const int32_t *orders, const int32_t *quad)
+{
+    const p2s_terms &a = p->terms;
+    return a.problem == t->problem && a.material == t->material && a.precision == t->precision &&
+           a.method == t->method && a.stiff_scale == t->stiff_scale && a.mass_scale == t->mass_scale &&
+           p->E == E && (E == 0 || (std::memcmp(p->orders.data(), orders, sizeof(int32_t) * E) == 0 &&
+                                    std::memcmp(p->quad.data(), quad, sizeof(int32_t) * 3 * E) == 0));
+}
+
 int p2s_fill_element_matrices(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const double *nodes,
                               const double *material, const int32_t *orders, const int32_t *quad,
                               double *out, uint32_t *status, void *stream)
 {
+    if (!ctx) return P2S_EINVAL;
+    if (!terms) return fail(ctx, P2S_EINVAL, "fill: NULL terms");
+    if (E < 0 || (E > 0 && (!orders || !quad))) return fail(ctx, P2S_EINVAL, "fill: bad E or NULL orders/quad");
     p2s_plan plan = nullptr;
-    int r = p2s_plan_create(ctx, terms, E, orders, quad, &plan);
-    if (r != P2S_OK) return r;
-    r = p2s_plan_execute(plan, nodes, material, out, status, stream);
-    hipStreamSynchronize((hipStream_t)stream);
-    p2s_plan_destroy(plan);
-    return r;
+    for (size_t i = 0; i < ctx->fill_cache.size(); ++i)
+        if (same_shape(ctx->fill_cache[i], terms, E, orders, quad)) {
+            plan = ctx->fill_cache[i];
+            // most recently used last
+            ctx->fill_cache.erase(ctx->fill_cache.begin() + i);
+            ctx->fill_cache.push_back(plan);
+            break;
+        }
+    if (!plan) {
+        int r = p2s_plan_create(ctx, terms, E, orders, quad, &plan);
+        if (r != P2S_OK) return r;
+        if (ctx->fill_cache.size() >= FILL_CACHE_PLANS) {
+            // the least recently used plan goes; hipFree inside waits for
+            // the device, so work still queued on it completes first
+            p2s_plan_destroy(ctx->fill_cache.front());
+            ctx->fill_cache.erase(ctx->fill_cache.begin());
+        }
+        ctx->fill_cache.push_back(plan);
+    }
+    return p2s_plan_execute(plan, nodes, material, out, status, stream);
 }
 
 int p2s_plan_set_schedule(p2s_plan plan, int mode, int wgs_per_cu)

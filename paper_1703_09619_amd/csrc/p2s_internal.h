@@ -137,7 +137,6 @@ enum MatKind : int { MAT_SINCOSEXP = 0, MAT_ROTDIAG = 1, MAT_PLANEWAVE = 2, ALPH
 constexpr uint32_t P2S_STATUS_DETJ_BIT = 1u;
 constexpr uint32_t P2S_STATUS_NONFINITE_BIT = 2u;
 constexpr uint32_t P2S_STATUS_FALLBACK_BIT = 4u;
-constexpr uint32_t P2S_STATUS_TAIL_BIT = 8u;
 
 // Learned quadrature order: network shape and parameter layout (FP32).
 // Weights are stored input-major, W[i][o]: y_o = sum_i x_i W[i][o] + b_o.

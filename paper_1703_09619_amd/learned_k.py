@@ -205,7 +205,7 @@ def evaluate(ctx, w, p_cover, theta, tol, k_direct=KMAX + 1, reps=3):
     rules = plan.rules()
     return dict(E=int(w.E), full_s=t_full, learned_s=t_learned, speedup=t_full / t_learned,
                 max_err=float(err.max()), frac_over_tol=float((err > tol).mean()),
-                fallback=float(((stn & 4) != 0).mean()), tail_flag=float(((stn & 8) != 0).mean()),
+                fallback=float(((stn & 4) != 0).mean()),
                 mean_points=float(np.prod(rules, axis=1).mean()), mean_rule=rules.mean(0).tolist())
 
 

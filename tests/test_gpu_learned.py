@@ -92,6 +92,34 @@ def test_adam_step_matches_reference(env):
     assert np.abs(p1 - pr)[big].max() <= 1e-6
 
 
+def test_adam_six_steps_match_reference(env):
+    """Six training steps on one batch against six steps of the FP64
+    reference (gradient + Adam with bias correction at steps 1..6, the
+    reference's Adam pinned by the constant-gradient closed form)."""
+    torch, mlp, ctx = env["torch"], env["mlp"], env["ctx"]
+    ctx.mlp_init(seed=9, max_batch=512)
+    p = ctx.mlp_params().astype(np.float64)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((128, 85)).astype(np.float32)
+    y = rng.integers(0, 19, size=(128, 3)).astype(np.int32)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    m, v = np.zeros_like(p), np.zeros_like(p)
+    lr = 1e-3
+    gmin = np.full_like(p, np.inf)
+    for t in range(1, 7):
+        _, g = mlp.loss_and_grad(p, x.astype(np.float64), y)
+        gmin = np.minimum(gmin, np.abs(g))
+        p, m, v = mlp.adam(p, g, m, v, t, lr)
+        ctx.mlp_train_step(xd, yd, lr, loss)
+    pg = ctx.mlp_params().astype(np.float64)
+    # parameters whose gradient stayed away from zero (elsewhere the FP32
+    # direction g/|g| is not determined by the data)
+    big = gmin > 1e-4
+    assert big.sum() > 1000
+    assert np.abs(pg - p)[big].max() <= 2e-6
+
+
 def test_predict_matches_reference_choice(env):
     torch, mlp, ctx = env["torch"], env["mlp"], env["ctx"]
     p = rand_params(mlp, 5)

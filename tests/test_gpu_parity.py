@@ -330,3 +330,126 @@ def test_direct_quadrature_method(env, problem, N, Q):
     """The GPU direct-quadrature baseline (eq. (2) without eq. (3))."""
     w = make_small(env, problem, N, 2, Q, seed=300 + N)
     check_against_oracle(env, w, method=1)
+
+
+def test_fill_element_matrices_one_shot(env):
+    """p2s_fill_element_matrices through the C ABI: all 64 elements of the
+    scalar N=4 workload and a subset of the vector N=6 workload against the
+    oracle; a repeated call of the same shape (cached plan) gives the same
+    bits; nine shapes in turn (one eviction) stay correct."""
+    torch, W, ctx = env["torch"], env["W"], env["ctx"]
+    for w in (W.make("scalar_n4"), W.subset(W.make("vector_n6", E=16), np.arange(8))):
+        nodes = torch.from_numpy(w.nodes).cuda()
+        mat = torch.from_numpy(w.mat).cuda()
+        out, st = ctx.fill_element_matrices(w.problem, w.material, nodes, mat, w.orders, w.quad)
+        out2, st2 = ctx.fill_element_matrices(w.problem, w.material, nodes, mat, w.orders, w.quad)
+        torch.cuda.synchronize()
+        assert torch.equal(out, out2) and torch.equal(st, st2)
+        ref, roff, rst = env["oracle"].fill(w.problem, w.material, w.nodes, w.mat, w.orders, w.quad)
+        assert np.array_equal(st.cpu().numpy(), rst.astype(np.int32))
+        errs = rel_errors(out.cpu().numpy(), ref, roff)
+        print("one-shot", w.name, "max rel err %.3e" % errs.max(), flush=True)
+        assert errs.max() <= TOL
+    base = W.make("scalar_n4")
+    ref, roff, _ = env["oracle"].fill(base.problem, base.material, base.nodes[:9], base.mat[:9],
+                                      base.orders[:9], base.quad[:9])
+    for E in range(1, 10):
+        sub = W.subset(base, np.arange(E))
+        out, _ = ctx.fill_element_matrices(sub.problem, sub.material, torch.from_numpy(sub.nodes).cuda(),
+                                           torch.from_numpy(sub.mat).cuda(), sub.orders, sub.quad)
+        torch.cuda.synchronize()
+        errs = rel_errors(out.cpu().numpy(), ref[:int(roff[E])], roff[:E + 1])
+        assert errs.max() <= TOL, E
+
+
+def test_scalar_mixed_full_size_autotuned(env):
+    """The 20000-element mixed-order workload (N ~ U{2..8}, Q = 2N) under
+    the schedule the autotuner picks: one sampled element per order class
+    against the oracle, symmetry of those blocks, status clean."""
+    torch, W = env["torch"], env["W"]
+    w = W.make("scalar_mixed")
+    plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
+    nodes = torch.from_numpy(w.nodes).cuda()
+    mat = torch.from_numpy(w.mat).cuda()
+    out = torch.empty(int(plan.offsets[-1]), dtype=torch.float64, device="cuda")
+    st = torch.empty(w.E, dtype=torch.int32, device="cuda")
+    plan.autotune(nodes, mat, out, st)
+    print("schedule", plan.schedule(), flush=True)
+    out.fill_(float("nan"))
+    plan.execute(nodes, mat, out, st)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    assert not bool(torch.isnan(out).any())
+    rng = np.random.default_rng(2024)
+    pick = sorted(int(rng.choice(np.nonzero(w.orders == N)[0])) for N in range(2, 9))
+    sub = W.subset(w, pick)
+    ref, roff, _ = env["oracle"].fill(sub.problem, sub.material, sub.nodes, sub.mat, sub.orders, sub.quad)
+    off = plan.offsets
+    for i, e in enumerate(pick):
+        x = out[int(off[e]):int(off[e + 1])].cpu().numpy()
+        y = ref[roff[i]:roff[i + 1]]
+        n = int(round(len(y) ** 0.5))
+        err = np.linalg.norm(x - y) / np.linalg.norm(y)
+        print("element", e, "N", int(w.orders[e]), "rel err %.3e" % err, flush=True)
+        assert err <= TOL
+        X = x.reshape(n, n)
+        assert np.abs(X - X.T).max() <= 1e-13 * np.abs(X).max()
+
+
+def test_vector_n8_full_size_sampled(env):
+    """The 8192-element vector N=8 workload (1344 dofs, 16^3 points), FP64:
+    first, middle and last element against the oracle, symmetry of every
+    element matrix, and bitwise repeatability (per-element integer
+    checksums of the bits, so that one output buffer suffices)."""
+    torch, W = env["torch"], env["W"]
+    w = W.make("vector_n8")
+    plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
+    nodes = torch.from_numpy(w.nodes).cuda()
+    mat = torch.from_numpy(w.mat).cuda()
+    nd = 1344
+    out = torch.empty(w.E * nd * nd, dtype=torch.float64, device="cuda")
+    st = torch.empty(w.E, dtype=torch.int32, device="cuda")
+    plan.execute(nodes, mat, out, st)
+    torch.cuda.synchronize()
+    cks1 = out.view(torch.int64).view(w.E, -1).sum(1)
+    plan.execute(nodes, mat, out, st)
+    torch.cuda.synchronize()
+    cks2 = out.view(torch.int64).view(w.E, -1).sum(1)
+    assert torch.equal(cks1, cks2)
+    assert int(st.abs().sum()) == 0
+    M = out.view(w.E, nd, nd)
+    worst = 0.0
+    for c in range(0, w.E, 128):
+        blk = M[c:c + 128]
+        asym = (blk - blk.transpose(1, 2)).abs().amax(dim=(1, 2)) / blk.abs().amax(dim=(1, 2))
+        worst = max(worst, float(asym.max()))
+    print("max asymmetry %.3e" % worst, flush=True)
+    assert worst <= 1e-13
+    pick = [0, w.E // 2, w.E - 1]
+    sub = W.subset(w, pick)
+    ref, roff, _ = env["oracle"].fill(sub.problem, sub.material, sub.nodes, sub.mat, sub.orders, sub.quad)
+    for i, e in enumerate(pick):
+        x = M[e].cpu().numpy().reshape(-1)
+        y = ref[roff[i]:roff[i + 1]]
+        err = np.linalg.norm(x - y) / np.linalg.norm(y)
+        print("element", e, "rel err %.3e" % err, flush=True)
+        assert err <= TOL
+
+
+def test_nonfinite_status(env):
+    """A sampled coupling field holding a NaN or an infinity at one point
+    makes that element's matrix non-finite: its status carries
+    P2S_STATUS_NONFINITE, the other elements stay clean."""
+    torch, W, p2s = env["torch"], env["W"], env["p2s"]
+    rng = np.random.default_rng(17)
+    for problem, F in ((0, 7), (1, 12)):
+        N, Q, E = 4, (6, 5, 7), 4
+        a = rng.standard_normal((E, F, int(np.prod(Q))))
+        a[1, F - 1, 17] = float("nan")
+        a[3, 0, 3] = float("inf")
+        w = W.Workload(name="nonfinite", problem=problem, material=W.ALPHA_SAMPLED, E=E,
+                       nodes=np.zeros((E, 27, 3)), mat=a.reshape(E, -1),
+                       orders=np.full(E, N, np.int32), quad=np.tile(np.array(Q, np.int32), (E, 1)))
+        out, off, st, _ = gpu_fill(env, w)
+        assert st[0] == 0 and st[2] == 0
+        assert st[1] & p2s.STATUS_NONFINITE and st[3] & p2s.STATUS_NONFINITE

@@ -61,3 +61,23 @@ def test_adam_first_step_is_signed_lr():
     p1, m, v = mlp.adam(p, g, np.zeros(4), np.zeros(4), 1, 0.1)
     assert np.allclose(p1[:3], -0.1 * np.sign(g[:3]), atol=1e-7)
     assert p1[3] == 0.0
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the first and second moments are
+    m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the bias-corrected
+    estimates are exactly g and g^2 at every step t, and each step moves a
+    parameter by lr * g / (|g| + eps): after T steps the displacement is
+    T lr g / (|g| + eps).  A wrong bias-correction power, beta or step index
+    breaks this from the second step on."""
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal(16) * np.logspace(-3, 2, 16)
+    p0 = rng.standard_normal(16)
+    lr, eps = 3e-3, 1e-8
+    p, m, v = p0.copy(), np.zeros(16), np.zeros(16)
+    for t in range(1, 8):
+        p, m, v = mlp.adam(p, g, m, v, t, lr, eps=eps)
+        assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-13, atol=0)
+        assert np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12, atol=0)
+        step_ref = p0 - t * lr * g / (np.abs(g) + eps)
+        assert np.abs(p - step_ref).max() <= 1e-13 * t

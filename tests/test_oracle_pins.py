@@ -216,6 +216,104 @@ def test_vector_universal_matrix(oracle_mod, N):
     assert np.abs(A - ref).max() < 1e-14
 
 
+# ---------------------------------------------------------------- materials
+def _one_d(Q, fa, na, fb, nb, weight):
+    """sum_a w_a X_m(t_a) Y_n(t_a) weight(t_a) on the Q-point Gauss rule
+    (numpy's rule and Legendre series): [na][nb], complex if weight is."""
+    t, w = npleg.leggauss(Q)
+    wt = w * weight(t)
+    X = np.array([npleg.legval(t, _leg_series(m, fa)) for m in range(na)])
+    Y = np.array([npleg.legval(t, _leg_series(n, fb)) for n in range(nb)])
+    return (X * wt) @ Y.T
+
+
+def _kron3(a, b, c):
+    return np.kron(np.kron(a, b), c)
+
+
+def _scalar_separable(N, Q, ws, sK=1.0, sM=1.0):
+    """Scalar matrix on the undeformed cube (J = I/2: stiffness coefficient
+    eps/2, mass coefficient eps/8) for eps = sum_r c_r f_r(u) g_r(v) h_r(w),
+    ws = [(c_r, (f_r, g_r, h_r))]: Kronecker products of 1-D Gauss sums."""
+    ref = 0.0
+    for c, fs in ws:
+        Mx = [_one_d(Q[a], "phi", N, "phi", N, fs[a]) for a in range(3)]
+        Kx = [_one_d(Q[a], "dphi", N, "dphi", N, fs[a]) for a in range(3)]
+        ref = ref + c * (0.5 * sK * (_kron3(Kx[0], Mx[1], Mx[2]) + _kron3(Mx[0], Kx[1], Mx[2])
+                                     + _kron3(Mx[0], Mx[1], Kx[2])) + 0.125 * sM * _kron3(*Mx))
+    return ref
+
+
+def _x_of(t):
+    return 0.5 * (t + 1.0)  # nominal node (i,j,k) at 0.5*(i,j,k)
+
+
+@pytest.mark.parametrize("N,Q,kappa", [(3, (7, 8, 9), 2.3), (4, (9, 6, 8), 4 * math.pi)])
+def test_sincosexp_material_separable(oracle_mod, N, Q, kappa):
+    """eps = 1 + 0.5 sin(kappa x) cos(kappa y) exp(-z) on the undeformed
+    cube is a sum of two separable terms, and the tensor Gauss rule
+    factorizes: the matrix is a sum of Kronecker products of weighted 1-D
+    sums.  Pins the 0.5 amplitude, the sin/cos/exp factors and their axes,
+    and the constant 1."""
+    one = lambda t: np.ones_like(t)
+    ws = [(1.0, (one, one, one)),
+          (0.5, (lambda t: np.sin(kappa * _x_of(t)), lambda t: np.cos(kappa * _x_of(t)),
+                 lambda t: np.exp(-_x_of(t))))]
+    for sK, sM in ((1.0, 1.0), (0.0, 1.0), (1.0, 0.0)):
+        (A,) = run_fill(oracle_mod, SCALAR, MAT_SINCOSEXP, nominal_nodes(), [kappa], N, Q, sK, sM)
+        ref = _scalar_separable(N, Q, ws, sK, sM)
+        assert np.abs(A - ref).max() <= 2e-15 * np.abs(ref).max() * N ** 3
+
+
+@pytest.mark.parametrize("N,Q", [(3, (6, 7, 8)), (5, (10, 9, 11))])
+def test_planewave_material_separable(oracle_mod, N, Q):
+    """eps = 1 + 0.8 sin(k.x + phase) = 1 + 0.8 Im(e^{i phase} prod_a
+    e^{i k_a x_a}) on the undeformed cube: complex separable terms."""
+    k = np.array([3.1, -5.7, 8.2])
+    ph = 0.9
+    one = lambda t: np.ones_like(t)
+    (A,) = run_fill(oracle_mod, SCALAR, MAT_PLANEWAVE, nominal_nodes(), list(k) + [ph], N, Q)
+    base = _scalar_separable(N, Q, [(1.0, (one, one, one))])
+    wave = _scalar_separable(N, Q, [(np.exp(1j * ph), tuple(
+        (lambda t, ka=ka: np.exp(1j * ka * _x_of(t))) for ka in k))])
+    ref = base + 0.8 * np.imag(wave)
+    assert np.abs(A - ref).max() <= 2e-15 * np.abs(ref).max() * N ** 3
+
+
+@pytest.mark.parametrize("N,Q", [(3, (6, 7, 5)), (4, (8, 7, 9))])
+def test_rotdiag_material_separable_vector_mass(oracle_mod, N, Q):
+    """Vector mass on the undeformed cube: coefficient detJ J^-1 eps J^-T =
+    eps/2 with eps_ij = sum_a R_ai d_a R_aj, d_a = 1 + 0.5 Im(e^{i 2 pi a/3}
+    prod_c e^{i k_c x_c}); block (i,j) takes psi on axis i (test) and axis j
+    (trial), phi elsewhere.  Pins the rotation's index order, the three
+    phase shifts and the amplitude."""
+    rng = np.random.default_rng(21)
+    R, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    if np.linalg.det(R) < 0:
+        R[:, 0] *= -1
+    k = np.array([2.7, -1.9, 4.4])
+    (A,) = run_fill(oracle_mod, VECTOR, MAT_ROTDIAG, nominal_nodes(), list(R.reshape(-1)) + list(k),
+                    N, Q, 0.0, 1.0)
+    one = lambda t: np.ones_like(t)
+    wave = tuple((lambda t, ka=ka: np.exp(1j * ka * _x_of(t))) for ka in k)
+    dims = lambda g: [N - 1 if ax == g else N for ax in range(3)]
+    fam = lambda g, ax: "psi" if ax == g else "phi"
+    blocks = [[None] * 3 for _ in range(3)]
+    for i in range(3):
+        for j in range(3):
+            def kr(fs):
+                return _kron3(*[_one_d(Q[ax], fam(i, ax), dims(i)[ax], fam(j, ax), dims(j)[ax], fs[ax])
+                                for ax in range(3)])
+            K0, Kw = kr((one, one, one)), kr(wave)
+            blk = 0.0
+            for a in range(3):
+                blk = blk + R[a, i] * R[a, j] * (K0 + 0.5 * np.imag(np.exp(2j * math.pi * a / 3) * Kw))
+            blocks[i][j] = 0.5 * blk
+    ref = np.block(blocks)
+    assert A.shape == ref.shape
+    assert np.abs(A - ref).max() <= 1e-14 * np.abs(ref).max() * N
+
+
 # ---------------------------------------------------------------- E1
 @pytest.mark.parametrize("N", [3, 4])
 def test_curved_mass_exact_at_q_n_plus_2(oracle_mod, N):
