@@ -72,6 +72,25 @@ def direct_flops_per_element(problem: int, N: int, Q) -> int:
     return 2 * (nd * (nd + 1) // 2) * int(np.prod(Q)) * terms
 
 
+def direct_sf_flops_per_element(problem: int, N: int, Q: int) -> int:
+    """Algorithmic FP64 flops of sum-factorized direct quadrature per
+    element (rule Q per axis), in the order the kernels take the axes:
+    per coupling term of a block (I, J >= I), stage A contracts u
+    (nm_I nm_J Q^3 multiply-adds), stage B v (nm_I nm_J nn_I nn_J Q^2),
+    stage C w (nm_I nm_J nn_I nn_J np_I np_J Q); in a diagonal block only
+    m2 >= m1.  Scalar: one block of 10 terms; vector: six blocks of 5."""
+    def dims(g):
+        return [N - 1 if (problem == 1 and ax == g) else N for ax in range(3)]
+    blocks = [(0, 0)] if problem == 0 else [(i, j) for i in range(3) for j in range(i, 3)]
+    terms = 10 if problem == 0 else 5
+    macs = 0
+    for i, j in blocks:
+        di, dj = dims(i), dims(j)
+        pairs = sum(dj[0] - (m1 if i == j else 0) for m1 in range(di[0]))
+        macs += terms * pairs * (Q ** 3 + di[1] * dj[1] * Q ** 2 + di[1] * dj[1] * di[2] * dj[2] * Q)
+    return 2 * macs
+
+
 TRAFFIC_PROFILES = {("vector_n6", "fp64"): "profiles/k_contract_vector_n6.md"}
 
 
@@ -431,6 +450,37 @@ def main():
                          "algorithmic_flops": flops, "kernel_ms": round(dst_ms, 4)}}
         del dout
         log("direct baseline done")
+    Nh = int(w.orders[0])
+    if len(set(w.orders.tolist())) == 1 and (w.quad == 2 * Nh).all() and not split and learned is None:
+        # sum-factorized direct quadrature of every entry on the whole batch
+        # (the strong baseline: same discrete matrix, dense tables at the
+        # 2N Gauss points instead of moments and linearization tables)
+        splan = ctx.plan(w.problem, w.material, w.orders, w.quad, method=p2s.METHOD_DIRECT_SF)
+        sout = torch.empty_like(out)
+        sst = torch.empty_like(status)
+        splan.execute(nodes, mat, sout, sst)
+        torch.cuda.synchronize()
+        splan.profile(True)
+        d0 = time.perf_counter()
+        for _ in range(args.steps):
+            splan.execute(nodes, mat, sout, sst)
+        torch.cuda.synchronize()
+        d1 = time.perf_counter()
+        sst_ms = splan.profile_read()["contraction"][0] / args.steps
+        serr = ctx.rel_error(sout, out, offsets=torch.from_numpy(plan.offsets).to(dev)).cpu().numpy()
+        flops = w.E * direct_sf_flops_per_element(w.problem, Nh, int(w.quad[0, 0]))
+        tf = flops / (sst_ms * 1e-3) / 1e12
+        sms = (d1 - d0) * 1e3 / args.steps
+        result["gpu_direct_sum_factorized"] = {
+            "value": round(w.E / (sms * 1e-3), 1), "unit": "element matrices/s", "elements": w.E,
+            "ms_per_step": round(sms, 4), "p2s_speedup": round(sms / ms_per_step, 3),
+            "max_rel_frobenius_diff_vs_p2s": float(serr.max()),
+            "roofline": {"bound": "fp64", "kernel": "k_contract<%d,%d,I,J,true> (blocks J >= I)" % (w.problem, Nh),
+                         "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / FP64_PEAK_TFLOPS, 4), "algorithmic_flops": flops,
+                         "stage_ms": round(sst_ms, 4)}}
+        del sout, splan
+        log("sum-factorized direct baseline done")
 
     if not args.no_cpu_baseline:
         import oracle

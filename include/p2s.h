@@ -94,9 +94,15 @@ typedef enum {
  * accumulation in FP64. */
 typedef enum { P2S_FP64 = 0, P2S_SPLIT_FP32 = 1 } p2s_precision;
 
-/* Method: product-to-sum (the paper's method) or direct quadrature of
- * eq. (2) on the GPU (the baseline the paper compares against). */
-typedef enum { P2S_METHOD_P2S = 0, P2S_METHOD_DIRECT = 1 } p2s_method;
+/* Method: product-to-sum (the paper's method, Section II eqs. (3)-(4)),
+ * or one of two GPU baselines computing the same discrete matrix of eq. (2):
+ *  DIRECT     direct quadrature, every entry a full 3-D Gauss sum (the
+ *             method the paper compares against, Section IV);
+ *  DIRECT_SF  sum-factorized direct quadrature: the Gauss sum taken one
+ *             axis at a time with dense tables of weighted basis products
+ *             at the points.  Rules of exactly 2N points on every axis
+ *             (P2S_EQUAD otherwise); FP64. */
+typedef enum { P2S_METHOD_P2S = 0, P2S_METHOD_DIRECT = 1, P2S_METHOD_DIRECT_SF = 2 } p2s_method;
 
 typedef struct {
     int32_t problem;     /* p2s_problem                      */
@@ -234,27 +240,30 @@ int p2s_mlp_predict(p2s_ctx ctx, int64_t B, const float *x, float p_cover, int32
  * runs the network, chooses per axis the smallest K whose predicted
  * cumulative probability reaches p_cover (K >= k_direct: the full rule at
  * once; k_direct > P2S_KMAX disables that), samples the coupling factor with
- * the chosen rules and checks the tail.  Along each axis the moment stage
- * takes, on every line it contracts (samples for u, u-moments for v,
- * (u,v)-moments for w), the discrete Legendre coefficients of the four
- * highest degrees the rule resolves; their decay extrapolated to the first
- * degree the moments of eq. (4) can alias, relative to the largest value of
- * that tensor, is the axis statistic.  Its maximum over the axes sampled
- * below the full rule is the element's tail value; above theta the element
- * is sampled again with the full rule (status P2S_STATUS_FALLBACK).  Axes
- * already at the full rule take no statistic.  Orders up to 6 (P2S_EORDER
- * otherwise).  Allocates its workspace here; enable = 0 restores the plan's
- * own rules. */
+ * the chosen rules and checks the tail.  For each axis x sampled below the
+ * full rule and each field, the tail statistic takes the discrete Legendre
+ * coefficients along x of the four highest degrees the rule resolves,
+ * projected on the other two axes onto the moment degrees of eq. (4)
+ * (T_x[j] below); their decay extrapolated to the first degree the moments
+ * can alias, relative to the largest moment magnitude, is the axis value,
+ * and its maximum over those axes the element's tail value.  Above theta
+ * the element is sampled again with the full rule (status
+ * P2S_STATUS_FALLBACK).  Axes already at the full rule take no statistic.
+ * Orders up to 6 (P2S_EORDER otherwise).  Allocates its workspace here;
+ * enable = 0 restores the plan's own rules. */
 int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, int k_direct, double theta);
 /* Tail records of the moment stage at the plan's own rules (coupling and
  * moments only; no contraction): records [device][E][F][16], per field
- * env[axis][j] at axis*4+j, j = 0..3 for the degrees Q-1..Q-4 of that axis
- * (axis 0 = u on the samples, 1 = v on the u-moments, 2 = w on the
- * (u,v)-moments), and the largest magnitude of the tensor each axis was examined
- * on at 12+axis; entry 15 is zero, and so is every entry of an axis sampled
- * with P2S_KMAX points or more.  The statistic of p2s_plan_set_learned
- * is computed from these.  Product-to-sum plans of orders up to 6;
- * allocates its workspace on first use. */
+ * env[axis][j] at axis*4+j, the largest magnitude of
+ *   T_u[j][l][q] = sum t_j(a) W[l](b) W[q](c) alpha(a,b,c)   (axis 0),
+ *   T_v[k][j][q], T_w[k][l][j]                                (axes 1, 2),
+ * t_j(a) = (2d+1)/2 w_a L_d(x_a) for degree d = Q-1-j of that axis's rule,
+ * W[l](b) = w_b L_l(x_b) for the moment degrees l < 2N-1; at 12+axis the
+ * largest magnitude of the field's moment tensor; entry 15 is zero, and so
+ * is every entry of an axis sampled with P2S_KMAX points or more.  The
+ * statistic of p2s_plan_set_learned is computed from these.
+ * Product-to-sum plans of orders up to 6 whose moment stage can hold the
+ * tail rows (P2S_EQUAD otherwise); allocates its workspace on first use. */
 int p2s_plan_tail_records(p2s_plan plan, const double *nodes, const double *material, double *records,
                           void *stream);
 /* Rules used by the last execution: quad [host][E][3]. */

@@ -3,28 +3,29 @@
 TEST INFRASTRUCTURE ONLY (the test-suite compares the library's tail
 records and decisions with it).  Shares no code with the product library.
 
-With Q Gauss points along an axis the discrete Legendre coefficient of
-degree d of a line of values y_a is
-    c_d = (2d+1)/2 * sum_a w_a L_d(x_a) y_a,
-which equals the exact Legendre coefficient when the line is a polynomial of
-degree <= Q-1 (Gauss exactness, degree 2d <= 2Q-2).  The moment integrals of
-eq. (4) of degree k < K_m = 2N-1 along an axis are exact unless the sampled
-function has Legendre content of degree >= 2Q-k along it.
-
-Per field, the record holds for each axis the envelope (largest magnitude
-over lines) of c_{Q-1}, ..., c_{Q-4} and the largest magnitude of the tensor
-whose lines were taken:
-    axis u: lines of the samples alpha[.][b][c];
-    axis v: lines of the u-moments P1[k][.][c] = sum_a W_u[k][a] alpha[a][b][c];
-    axis w: lines of the (u,v)-moments P2[k][l][.] = sum_b W_v[l][b] P1[k][b][c];
-with W[k][a] = w_a L_k(x_a), k, l < K_m.  An axis sampled with the full
-rule (Q >= qfull) records zeros.  The element's tail value combines, over
-the fields, the envelopes A_j and scale S of each reduced axis as
-    r2 = min(1, max(A_1/A_3, A_2/A_4)),
-    est = max(A_1, A_2) * r2 ** max(0, (Q - K_m + 2)/2),
+What the statistic measures.  The moments of eq. (4) are taken with Q Gauss
+points per axis; along an axis, the moment of degree k is exact unless the
+coupling factor, seen through the moment degrees of the other two axes, has
+Legendre content along that axis at degrees >= 2Q - k.  The content a
+Q-point rule can still resolve is the discrete Legendre coefficient
+    c_d = (2d+1)/2 * sum_a w_a L_d(x_a) y_a      (d <= Q-1),
+exact for polynomial lines of degree <= Q-1.  For each axis x sampled below
+the full rule, each field s and the four highest resolvable degrees
+d = Q_x-1-j (j = 0..3), the statistic takes
+    T_x[j] = the degree-d coefficient along x of alpha_s, projected on the
+             other two axes onto the Legendre moments of degree < K_m = 2N-1,
+e.g. T_u[j][l][q] = sum_{a,b,c} t_j(a) W_v[l][b] W_w[q][c] alpha_s(a,b,c)
+with t_j(a) = (2d+1)/2 w_a L_d(x_a) and W[l][b] = w_b L_l(x_b).  It is the
+same for every axis (no axis order is involved).  The record of a field
+holds the envelopes A_x[j] = max |T_x[j][.][.]| and, for every reduced
+axis, the scale S = max |I_s| of the field's moment tensor.  The element's
+tail value combines them over the fields as
+    r2 = min(1, max(A_0/A_2, A_1/A_3)),
+    est = max(A_0, A_1) * r2 ** max(0, (Q - K_m + 2)/2),
     tau = max over reduced axes of est / S,
 i.e. the top resolvable content extrapolated at its own two-degree decay to
-the first degree the moments can alias.
+the first degree the moments can alias.  Axes sampled with the full rule
+(Q >= qfull) take no statistic: a refill could not change them.
 """
 from __future__ import annotations
 
@@ -60,33 +61,37 @@ def _tail_rows(Q):
     return rows
 
 
+def _moment_rows(Q, Km):
+    """w_a L_k(x_a) for k < Km: [Km][Q]."""
+    x, w = _rule(Q)
+    return _legendre_rows(x, Km) * w
+
+
 def records(alpha, Qu, Qv, Qw, N, qfull=24):
     """Tail records [F][16] of one element from its coupling samples
-    alpha [F][Qu*Qv*Qw] (index (a*Qv + b)*Qw + c)."""
+    alpha [F][Qu*Qv*Qw] (index (a*Qv + b)*Qw + c): env[axis][j] at axis*4+j,
+    the scale at 12+axis (zeros for axes at the full rule), 15 unused."""
     Km = 2 * N - 1
     F = alpha.shape[0]
     A = alpha.reshape(F, Qu, Qv, Qw)
+    Wu, Wv, Ww = _moment_rows(Qu, Km), _moment_rows(Qv, Km), _moment_rows(Qw, Km)
+    Tu, Tv, Tw = _tail_rows(Qu), _tail_rows(Qv), _tail_rows(Qw)
     out = np.zeros((F, REC))
-    xu, wu = _rule(Qu)
-    xv, wv = _rule(Qv)
-    Wu = _legendre_rows(xu, Km) * wu
-    Wv = _legendre_rows(xv, Km) * wv
     for f in range(F):
         a = A[f]
-        P1 = np.einsum("ka,abc->kbc", Wu, a)      # [Km][Qv][Qw]
-        P2 = np.einsum("lb,kbc->klc", Wv, P1)     # [Km][Km][Qw]
+        S = np.abs(np.einsum("ka,lb,qc,abc->klq", Wu, Wv, Ww, a, optimize=True)).max()
         if Qu < qfull:
-            c = np.einsum("ja,abc->jbc", _tail_rows(Qu), a)
-            out[f, 0:4] = np.abs(c).reshape(4, -1).max(1)
-            out[f, 12] = np.abs(a).max()
+            T = np.einsum("ja,lb,qc,abc->jlq", Tu, Wv, Ww, a, optimize=True)
+            out[f, 0:4] = np.abs(T).reshape(4, -1).max(1)
+            out[f, 12] = S
         if Qv < qfull:
-            c = np.einsum("jb,kbc->jkc", _tail_rows(Qv), P1)
-            out[f, 4:8] = np.abs(c).reshape(4, -1).max(1)
-            out[f, 13] = np.abs(P1).max()
+            T = np.einsum("ka,jb,qc,abc->jkq", Wu, Tv, Ww, a, optimize=True)
+            out[f, 4:8] = np.abs(T).reshape(4, -1).max(1)
+            out[f, 13] = S
         if Qw < qfull:
-            c = np.einsum("jc,klc->jkl", _tail_rows(Qw), P2)
-            out[f, 8:12] = np.abs(c).reshape(4, -1).max(1)
-            out[f, 14] = np.abs(P2).max()
+            T = np.einsum("ka,lb,jc,abc->jkl", Wu, Wv, Tw, a, optimize=True)
+            out[f, 8:12] = np.abs(T).reshape(4, -1).max(1)
+            out[f, 14] = S
     return out
 
 

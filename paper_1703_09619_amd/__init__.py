@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libp2s.so")
 SCALAR, VECTOR = 0, 1
 MAT_SINCOSEXP, MAT_ROTDIAG, MAT_PLANEWAVE, ALPHA_SAMPLED = 0, 1, 2, 3
 FP64, SPLIT_FP32 = 0, 1
-METHOD_P2S, METHOD_DIRECT = 0, 1
+METHOD_P2S, METHOD_DIRECT, METHOD_DIRECT_SF = 0, 1, 2
 FAM_PHI, FAM_DPHI, FAM_PSI = 0, 1, 2
 STATUS_DETJ, STATUS_NONFINITE, STATUS_FALLBACK = 1, 2, 4
 MAX_ORDER, MAX_Q = 8, 32

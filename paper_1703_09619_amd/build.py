@@ -5,6 +5,7 @@ Usage: python -m paper_1703_09619_amd.build  (or call build()).
 from __future__ import annotations
 
 import os
+import hashlib
 import shutil
 import subprocess
 import sys
@@ -17,8 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libp2s.so")
 
-HIP_SOURCES = ["p2s_api.hip", "p2s_kernels.hip", "p2s_contract.hip", "p2s_direct.hip", "p2s_learned.hip",
-               "p2s_split.hip"]
+HIP_SOURCES = ["p2s_api.hip", "p2s_kernels.hip", "p2s_contract.hip", "p2s_direct.hip", "p2s_direct_sf.hip",
+               "p2s_learned.hip", "p2s_split.hip"]
 CXX_SOURCES = ["p2s_tables.cpp"]
 ARCH = "gfx950"
 
@@ -42,18 +43,41 @@ def hip_flags():
             "-munsafe-fp-atomics"]
 
 
-def build(verbose: bool = False) -> str:
+def _headers_digest() -> str:
+    h = hashlib.sha256()
+    for d in (CSRC, INCLUDE):
+        for f in sorted(os.listdir(d)):
+            if f.endswith(".h"):
+                h.update(f.encode())
+                h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source and link libp2s.so.  With incremental=True
+    (development use) an object whose source, headers and flags are
+    unchanged since the last incremental build is reused from _build/."""
     hipcc = _hipcc()
     tmpdir = tempfile.mkdtemp(prefix="p2s_build_")
+    cache = os.path.join(ROOT, "_build")
+    hdr = _headers_digest() if incremental else ""
     objs = []
     cmds = []
-    for src in HIP_SOURCES:
+    for src, cmd0 in [(x, [hipcc, "-x", "hip", "-c"]) for x in HIP_SOURCES] + [(x, ["g++", "-c"]) for x in CXX_SOURCES]:
+        flags = common_flags() + (hip_flags() if cmd0[0] == hipcc else [])
         obj = os.path.join(tmpdir, src + ".o")
-        cmds.append([hipcc, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + common_flags() + hip_flags())
-        objs.append(obj)
-    for src in CXX_SOURCES:
-        obj = os.path.join(tmpdir, src + ".o")
-        cmds.append(["g++", "-c", os.path.join(CSRC, src), "-o", obj] + common_flags())
+        cmd = cmd0 + [os.path.join(CSRC, src), "-o", obj] + flags
+        if incremental:
+            key = hashlib.sha256((hdr + " ".join(cmd0 + flags)).encode() +
+                                 open(os.path.join(CSRC, src), "rb").read()).hexdigest()[:20]
+            cached = os.path.join(cache, "%s.%s.o" % (src, key))
+            if os.path.exists(cached):
+                objs.append(cached)
+                continue
+            os.makedirs(cache, exist_ok=True)
+            cmd[cmd.index(obj)] = cached
+            obj = cached
+        cmds.append(cmd)
         objs.append(obj)
 
     def run(cmd):
@@ -66,8 +90,9 @@ def build(verbose: bool = False) -> str:
         if err.strip() and verbose:
             print(err)
 
-    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
-        list(ex.map(run, cmds))
+    if cmds:
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            list(ex.map(run, cmds))
     tmp_lib = LIB + ".tmp%d" % os.getpid()
     run([hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp_lib] + objs)
     os.replace(tmp_lib, LIB)
@@ -76,4 +101,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -294,8 +294,18 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
     }
     if (problem == P2S_SCALAR && kind == P2S_MAT_ROTDIAG)
         return fail(ctx, P2S_EINVAL, "plan: the scalar problem takes an isotropic material");
-    if (terms->method != P2S_METHOD_P2S && terms->method != P2S_METHOD_DIRECT)
+    if (terms->method != P2S_METHOD_P2S && terms->method != P2S_METHOD_DIRECT &&
+        terms->method != P2S_METHOD_DIRECT_SF)
         return fail(ctx, P2S_EINVAL, "plan: bad method %d", terms->method);
+    if (terms->method == P2S_METHOD_DIRECT_SF) {
+        if (terms->precision != P2S_FP64)
+            return fail(ctx, P2S_EINVAL, "plan: sum-factorized direct quadrature is FP64");
+        for (int64_t e = 0; e < E; ++e)
+            if (orders[e] >= 2 && orders[e] <= P2S_MAX_ORDER &&
+                (quad[3 * e] != 2 * orders[e] || quad[3 * e + 1] != 2 * orders[e] || quad[3 * e + 2] != 2 * orders[e]))
+                return fail(ctx, P2S_EQUAD, "plan: sum-factorized direct quadrature takes rules of 2N Gauss points "
+                                            "per axis (element %lld: order %d)", (long long)e, orders[e]);
+    }
     if (terms->precision != P2S_FP64 && terms->precision != P2S_SPLIT_FP32)
         return fail(ctx, P2S_EINVAL, "plan: unsupported precision %d", terms->precision);
     if (terms->precision == P2S_SPLIT_FP32 && terms->method != P2S_METHOD_P2S)
@@ -504,6 +514,21 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         launch_coupling(problem, plan->d_desc, c.e0, c.count, nodes, material, plan->terms.material,
                         plan->mat_stride, ctx->d_tab, plan->d_alpha, status, nullptr, st);
         prof_end(plan, 0, st);
+        if (plan->terms.method == P2S_METHOD_DIRECT_SF && stop == STOP_FULL) {
+            prof_begin(plan, 2, st);
+            int r = 0;
+            if (plan->uniform)
+                r = launch_contract_dsf(problem, plan->N, plan->d_desc, nullptr, c.e0, c.count, ctx->d_tab,
+                                        plan->d_alpha, out, status, plan->terms.stiff_scale, plan->terms.mass_scale, st);
+            else
+                for (const auto &cl : c.classes)
+                    r |= launch_contract_dsf(problem, (int)cl[0], plan->d_desc, plan->d_elist, cl[1], cl[2],
+                                             ctx->d_tab, plan->d_alpha, out, status, plan->terms.stiff_scale,
+                                             plan->terms.mass_scale, st);
+            prof_end(plan, 2, st);
+            if (r != 0) return fail(ctx, P2S_EINVAL, "execute: no direct-quadrature kernel for this order");
+            continue;
+        }
         if (plan->terms.method == P2S_METHOD_DIRECT && stop == STOP_FULL) {
             prof_begin(plan, 3, st);
             launch_direct(problem, plan->N, plan->d_desc, c.e0, c.count, ctx->d_tab, plan->d_alpha, out,
@@ -638,6 +663,8 @@ int p2s_plan_tail_records(p2s_plan plan, const double *nodes, const double *mate
     p2s_ctx ctx = plan->ctx;
     if (plan->terms.method != P2S_METHOD_P2S) return fail(ctx, P2S_EINVAL, "tail records need the product-to-sum method");
     if (plan->maxN > TAIL_MAXN) return fail(ctx, P2S_EORDER, "tail records: orders up to %d", TAIL_MAXN);
+    if (plan->E > 0 && moments_smem_bytes(plan->maxN, plan->mshape.maxQw, plan->mshape.maxQvw, true) > LDS_LIMIT)
+        return fail(ctx, P2S_EQUAD, "tail records: rule too large for the moment stage with tail rows");
     if (plan->E > 0 && !plan->d_tailst) {
         HIP_TRY(ctx, hipSetDevice(ctx->device));
         const int64_t n = plan->E * num_fields(plan->terms.problem) * TAIL_REC;
@@ -1068,6 +1095,8 @@ int p2s_plan_set_learned(p2s_plan plan, int enable, float p_cover, int k_direct,
         return fail(ctx, P2S_EINVAL, "learned order: needs a uniform product-to-sum plan created with %d points "
                                      "per axis", MLP_KMAX);
     if (plan->N > TAIL_MAXN) return fail(ctx, P2S_EORDER, "learned order: orders up to %d", TAIL_MAXN);
+    if (moments_smem_bytes(plan->maxN, plan->mshape.maxQw, plan->mshape.maxQvw, true) > LDS_LIMIT)
+        return fail(ctx, P2S_EQUAD, "learned order: rule too large for the moment stage with tail rows");
     if (!(p_cover > 0.f && p_cover <= 1.f) || !(theta > 0.0) || k_direct < MLP_KMIN)
         return fail(ctx, P2S_EINVAL, "learned order: bad p_cover / k_direct / theta");
     if (!plan->d_lx && plan->E > 0) {

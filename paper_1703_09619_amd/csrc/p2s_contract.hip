@@ -1,447 +1,10 @@
 // p2s_contract.hip -- the contraction stage of the product-to-sum fill,
-// eq. (4) of the paper: M = sum_s sum_{k,l,q} Cu Cv Cw I_s, applied mode by
-// mode, for gfx950 (wave64).
-//
-// One kernel per component block (I, J >= I) and one workgroup per (element,
-// first-axis test index m1): it produces rows (m1, n1, p1) of component I
-// against component J (the element matrix is symmetric; the part below the
-// diagonal is stored as the mirror image).  Within a block the coupling terms are grouped: a group shares the (v, w)
-// family pairs, a run shares the w pair.
-//   stage A  A_g[m2][l][q] = sum_{s in g} sign_s sum_k Cu_s[m1][m2][k] I_s[k][l][q]
-//            one thread per (group, l, q); each moment is loaded once and
-//            reused for every m2                                     (LDS)
-//   stage B  B[q] += sum_l Cv_g[n1][n2][l] A_g[m2][l][q]  over the groups
-//            of a run; one lane per (m2, n1, n2)                   (registers)
-//   stage C  acc[p1][p2] += sum_q Cw_run[p1][p2][q] B[q]           (registers)
-// The term structure of every block is computed at compile time, so the
-// family pairs, fields and signs are constants; stage C's sparsity is
-// unrolled and its coefficients are scalar loads from a packed table.
-// The finished tile goes through LDS so that every store instruction writes
-// whole rows (1 KiB per wave instruction).
-#include <hip/hip_runtime.h>
-
-#include <type_traits>
-#include <utility>
-
-#include "p2s_internal.h"
-#include "p2s_kernels.h"
-#include "p2s_terms.h"
+// eq. (4) of the paper, for gfx950 (wave64): per-block launches of the
+// kernels in p2s_contract_impl.h over the moments, and a persistent
+// schedule for batches of mixed orders.
+#include "p2s_contract_impl.h"
 
 namespace p2s {
-
-// ---------------------------------------------------------------------------
-// Compile-time structure
-
-struct MaskTableC {
-    uint32_t m[NTYPE][MAXN][MAXN];
-    constexpr MaskTableC() : m()
-    {
-        for (int t = 0; t < NTYPE; ++t)
-            for (int a = 0; a < MAXN; ++a)
-                for (int b = 0; b < MAXN; ++b) m[t][a][b] = prod_mask(t / 3, a, t % 3, b);
-    }
-};
-__constant__ MaskTableC c_cmasks = MaskTableC();
-
-struct PackIndex {
-    int16_t before[MAXN + 1][NTYPE][MAXN][MAXN];
-    constexpr PackIndex() : before()
-    {
-        for (int n = 2; n <= MAXN; ++n)
-            for (int t = 0; t < NTYPE; ++t) {
-                int c = 0;
-                for (int p1 = 0; p1 < fam_dim(t / 3, n); ++p1)
-                    for (int p2 = 0; p2 < fam_dim(t % 3, n); ++p2) {
-                        before[n][t][p1][p2] = (int16_t)c;
-                        c += popcount32(prod_mask(t / 3, p1, t % 3, p2));
-                    }
-            }
-    }
-};
-constexpr PackIndex kPackIndex = PackIndex();
-
-struct PackOffsets {
-    int off[MAXN + 1][NTYPE];
-    constexpr PackOffsets() : off()
-    {
-        int o = 0;  // same running layout as packed_offset()
-        for (int n = 2; n <= MAXN; ++n)
-            for (int t = 0; t < NTYPE; ++t) {
-                off[n][t] = o;
-                o += (packed_count(t / 3, t % 3, n) + 1) & ~1;
-            }
-    }
-};
-constexpr PackOffsets kPackOffsets = PackOffsets();
-
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int cmin(int a, int b) { return a < b ? a : b; }
-
-// Compile-time shape of the work item of row component I against the column
-// components JB <= J < JE: lane count, LDS batching and store tile.
-template <int PROB, int N, int I, int JB = I, int JE = num_comp(PROB)>
-struct CS {
-    static constexpr int K = 2 * N - 1;
-    static constexpr int KS = K + 1;  // LDS row stride (16-byte aligned rows)
-    static constexpr int NC = num_comp(PROB);
-    static constexpr int NDOF = num_dofs(PROB, N);
-    static constexpr int NM_I = comp_dim(PROB, N, I, 0);
-    static constexpr int NN_I = comp_dim(PROB, N, I, 1);
-    static constexpr int NP_I = comp_dim(PROB, N, I, 2);
-    static constexpr int max_over_j(int what)
-    {
-        int m = 0;
-        for (int j = JB; j < JE; ++j) {
-            int v = 0;
-            if (what == 0) v = comp_dim(PROB, N, j, 0) * NN_I * comp_dim(PROB, N, j, 1);  // lane tasks
-            if (what == 1) v = make_block_c(PROB, I, j).ngroup;
-            if (what == 2) v = comp_dim(PROB, N, j, 1);
-            if (what == 3) v = comp_dim(PROB, N, j, 0) * comp_dim(PROB, N, j, 1) * comp_dim(PROB, N, j, 2);
-            if (what == 4) v = comp_dim(PROB, N, j, 1) * comp_dim(PROB, N, j, 2);
-            m = cmax(m, v);
-        }
-        return m;
-    }
-    // stage-B lanes in whole waves; from N = 7 on a CU holds a single
-    // workgroup, so whole groups of four waves keep its four SIMDs evenly
-    // loaded (and stage A's workers of two groups fit one pass)
-    static constexpr int THREADS =
-        N <= 6 ? ((max_over_j(0) + 63) / 64) * 64 : ((max_over_j(0) + 255) / 256) * 256;
-    static constexpr int MAXG = max_over_j(1);
-    static constexpr int A_DOUBLES = N * K * KS;                    // stage-A result per group
-    static constexpr int C_DOUBLES = NN_I * max_over_j(2) * KS;      // stage-B coefficients per group
-    static constexpr int GROUP_DOUBLES = A_DOUBLES + C_DOUBLES;
-    // groups per LDS batch: at most 40 KiB up to N = 6, so that four
-    // three-wave workgroups share a CU (the 168-VGPR bound of k_contract
-    // allows twelve waves per CU), ~62 KiB above
-    static constexpr int G = cmax(1, cmin(MAXG, (N <= 6 ? 5120 : 7936) / GROUP_DOUBLES));
-    static constexpr int TILE_MIN = NN_I * NP_I * (max_over_j(4) + 2);  // one m2 of the store tile
-    static constexpr int BUF = cmax(G * GROUP_DOUBLES, TILE_MIN);
-    static constexpr int SA = ((K * K + 63) / 64) * 64;              // stage-A workers per group
-};
-
-// constant address space: loads through it become scalar (SMEM) loads
-typedef __attribute__((address_space(4))) const double cdouble;
-
-template <int N, int X, int Y, int P1, int P2>
-__device__ __forceinline__ void stage_c_one(double (&acc)[N][N], const double (&bv)[2 * N - 1],
-                                            cdouble *__restrict__ tb)
-{
-    if constexpr (P1 < fam_dim(X, N) && P2 < fam_dim(Y, N)) {
-        constexpr uint32_t msk = prod_mask(X, P1, Y, P2);
-        constexpr int base = kPackIndex.before[N][3 * X + Y][P1][P2];
-#pragma unroll
-        for (int q = 0; q < 2 * N - 1; ++q)
-            if ((msk >> q) & 1u)
-                acc[P1][P2] = fma(tb[base + popcount32(msk & ((1u << q) - 1u))], bv[q], acc[P1][P2]);
-    }
-}
-
-template <int N, int X, int Y, int... Is>
-__device__ __forceinline__ void stage_c_all(double (&acc)[N][N], const double (&bv)[2 * N - 1],
-                                            cdouble *__restrict__ tb, std::integer_sequence<int, Is...>)
-{
-    (stage_c_one<N, X, Y, Is / N, Is % N>(acc, bv, tb), ...);
-}
-
-template <int N, int T>
-__device__ __forceinline__ void stage_c(double (&acc)[N][N], const double (&bv)[2 * N - 1],
-                                        const double *__restrict__ pack)
-{
-    constexpr int X = T / 3, Y = T % 3;
-    constexpr int off = kPackOffsets.off[N][T];
-    static_assert(off == packed_offset(N, X, Y), "packed table layout");
-    cdouble *tb = (cdouble *)(pack + off);
-    // keep the table base opaque to loop-invariant motion so that every
-    // coefficient is a scalar load at an immediate offset
-    asm volatile("" : "+s"(tb));
-    stage_c_all<N, X, Y>(acc, bv, tb, std::make_integer_sequence<int, N * N>{});
-}
-
-// Work-group id -> logical work item, so that consecutive items (the row
-// tiles of one element, which share its moment tensors) run on the same XCD:
-// the hardware deals work-group ids round-robin over the 8 XCDs.
-__device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t total_padded)
-{
-    const int64_t per = total_padded >> 3;
-    return (w & 7) * per + (w >> 3);
-}
-
-// One work item: rows (m1, n1, p1) of component I of element e against the
-// column components JB <= J < JE (JB >= I).  Called by all `nthreads` threads of a
-// workgroup (nthreads >= THREADS; extra threads take part in the barriers
-// and the cooperative loops only).  smem holds at least BUF doubles.
-template <int PROB, int N, int I, int JB = I, int JE = num_comp(PROB)>
-__device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int m1,
-                                              const double *__restrict__ tab, const double *__restrict__ mom,
-                                              double *__restrict__ out, uint32_t *__restrict__ status,
-                                              double sK, double sM, double *__restrict__ smem, int nthreads)
-{
-    using S = CS<PROB, N, I, JB, JE>;
-    constexpr int K = S::K, KS = S::KS, NC = S::NC, NDOF = S::NDOF, G = S::G;
-    constexpr int NN_I = S::NN_I, NP_I = S::NP_I;
-    const double *lin = tab + TAB_LIN;
-    const double *pack = tab + TAB_PACK;
-    const double *I0 = mom + d.mom_off;
-    double *obase = out + d.out_off;
-    const int tid = threadIdx.x;
-    const int rowbase = comp_offset(PROB, N, I) + m1 * NN_I * NP_I;
-    bool bad = false;
-
-    static_for<JB, JE>([&](auto Jc) {
-        constexpr int J = decltype(Jc)::value;
-        constexpr BlockC BK = BlockOf<PROB, I, J>::B;
-        constexpr int NM_J = comp_dim(PROB, N, J, 0), NN_J = comp_dim(PROB, N, J, 1),
-                      NP_J = comp_dim(PROB, N, J, 2);
-        constexpr int NBATCH = (BK.ngroup + G - 1) / G;
-        // symmetric: inside the diagonal block only m2 >= m1
-        const int m2lo = (J == I) ? m1 : 0;
-        const int nm = NM_J - m2lo;
-        const int T = nm * NN_I * NN_J;
-        const bool active = tid < T;
-        const int n2 = tid % NN_J;
-        const int m2 = m2lo + (tid / NN_J) % nm;
-        const int n1 = tid / (NN_J * nm);
-        double acc[N][N];
-#pragma unroll
-        for (int a = 0; a < N; ++a)
-#pragma unroll
-            for (int b = 0; b < N; ++b) acc[a][b] = 0.0;
-        double bsum[K];
-#pragma unroll
-        for (int q = 0; q < K; ++q) bsum[q] = 0.0;
-
-        static_for<0, NBATCH>([&](auto Bc) {
-            constexpr int g0 = decltype(Bc)::value * G;
-            constexpr int ng = cmin(G, BK.ngroup - g0);
-            double *Abuf = smem;                    // [ng][N][K][KS]
-            double *Cbuf = smem + ng * S::A_DOUBLES;  // [ng][NN_I*NN_J][KS]
-            // stage-B coefficient rows of this batch into LDS
-            for (int x = tid; x < ng * NN_I * NN_J * K; x += nthreads) {
-                const int gl = x / (NN_I * NN_J * K);
-                const int r = x - gl * (NN_I * NN_J * K);
-                const int nn = r / K, l = r - (r / K) * K;
-                const int a1 = nn / NN_J, a2 = nn - (nn / NN_J) * NN_J;
-                int tv = 0;
-                static_for<0, ng>([&](auto gc) {
-                    constexpr int g = decltype(gc)::value;
-                    if (gl == g) tv = BK.t[BK.gstart[g0 + g]].tv;
-                });
-                Cbuf[gl * (NN_I * NN_J * KS) + nn * KS + l] =
-                    lin[tv * LIN_STRIDE_T + a1 * LIN_STRIDE_M1 + a2 * KPAD + l];
-            }
-            // stage A: worker w -> (group gl, entry lq); gl is wave-uniform
-            for (int w = tid; w < ng * S::SA; w += nthreads) {
-                const int gl = w / S::SA;
-                const int lq = w - gl * S::SA;
-                if (lq < K * K) {
-                    double a[N];
-#pragma unroll
-                    for (int mm = 0; mm < N; ++mm) a[mm] = 0.0;
-                    static_for<0, ng>([&](auto gc) {
-                        constexpr int g = decltype(gc)::value;
-                        if (gl != g) return;
-                        static_for<BK.gstart[g0 + g], BK.gstart[g0 + g + 1]>([&](auto sc_) {
-                            constexpr TermC t = BK.t[decltype(sc_)::value];
-                            const double sc = (t.scale ? sM : sK) * (double)t.sign;
-                            const double *Ip = I0 + (int64_t)t.field * K * K * K + lq;
-                            double v[K];
-#pragma unroll
-                            for (int k = 0; k < K; ++k) v[k] = Ip[k * K * K];
-                            const double *Cu = lin + t.tu * LIN_STRIDE_T + m1 * LIN_STRIDE_M1;
-#pragma unroll
-                            for (int mm = 0; mm < NM_J; ++mm) {
-                                if (mm >= m2lo) {
-                                    const uint32_t mk = c_cmasks.m[t.tu][m1][mm];
-                                    double xs = 0.0;
-#pragma unroll
-                                    for (int k = 0; k < K; ++k)
-                                        if ((mk >> k) & 1u) xs = fma(Cu[mm * KPAD + k], v[k], xs);
-                                    a[mm] = fma(sc, xs, a[mm]);
-                                }
-                            }
-                        });
-                    });
-                    const int l = lq / K, q = lq - (lq / K) * K;
-                    double *Ab = Abuf + gl * S::A_DOUBLES + l * KS + q;
-#pragma unroll
-                    for (int mm = 0; mm < NM_J; ++mm)
-                        if (mm >= m2lo) Ab[mm * K * KS] = a[mm];
-                }
-            }
-            __syncthreads();
-            if (active) {
-                static_for<0, ng>([&](auto gc) {
-                    constexpr int g = decltype(gc)::value;
-                    constexpr int tv = BK.t[BK.gstart[g0 + g]].tv;
-                    constexpr int tw = BK.t[BK.gstart[g0 + g]].tw;
-                    // stage B: two set bits of the degree mask per step
-                    uint32_t ml = c_cmasks.m[tv][n1][n2];
-                    const double *crow = Cbuf + g * (NN_I * NN_J * KS) + (n1 * NN_J + n2) * KS;
-                    const double *arow = Abuf + g * S::A_DOUBLES + m2 * K * KS;
-                    while (ml) {
-                        const int l0 = __ffs(ml) - 1;
-                        ml &= ml - 1u;
-                        const bool two = ml != 0u;
-                        const int l1 = two ? __ffs(ml) - 1 : l0;
-                        ml &= two ? ml - 1u : ml;
-                        const double c0 = crow[l0];
-                        const double c1 = two ? crow[l1] : 0.0;
-                        const double2 *r0 = reinterpret_cast<const double2 *>(arow + l0 * KS);
-                        const double2 *r1 = reinterpret_cast<const double2 *>(arow + l1 * KS);
-#pragma unroll
-                        for (int h = 0; h < KS / 2; ++h) {
-                            const double2 x0 = r0[h], x1 = r1[h];
-                            bsum[2 * h] = fma(c1, x1.x, fma(c0, x0.x, bsum[2 * h]));
-                            if (2 * h + 1 < K) bsum[2 * h + 1] = fma(c1, x1.y, fma(c0, x0.y, bsum[2 * h + 1]));
-                        }
-                    }
-                    if constexpr (BK.cflag[g0 + g] != 0) {
-                        stage_c<N, tw>(acc, bsum, pack);
-#pragma unroll
-                        for (int q = 0; q < K; ++q) bsum[q] = 0.0;
-                    }
-                });
-            }
-            __syncthreads();
-        });
-
-        // coalesced stores through LDS: the tile holds all rows (n1, p1) of
-        // the item and the columns (m2, n2, p2) of a chunk of m2 >= m2lo, so
-        // that every mirrored row segment (the item's NR values) is written
-        // whole by one workgroup in one pass
-        {
-            constexpr int NR = NN_I * NP_I;      // tile rows
-            constexpr int CW = NN_J * NP_J;      // tile columns per m2
-            constexpr int CM = cmax(1, (S::BUF / NR - 1) / CW);  // m2 per chunk
-            static_assert(NR * ((CM * CW) | 1) <= S::BUF, "store tile exceeds the LDS buffer");
-            for (int ma = m2lo; ma < NM_J; ma += CM) {
-                const int mb = ma + CM < NM_J ? ma + CM : NM_J;
-                const int W = (mb - ma) * CW;    // tile width
-                // odd row stride: the transposed (mirror) reads below step two
-                // rows per lane, which an odd stride spreads over distinct banks
-                const int WS = W | 1;
-                if (active && m2 >= ma && m2 < mb) {
-                    double *tl = smem + n1 * NP_I * WS + ((m2 - ma) * NN_J + n2) * NP_J;
-#pragma unroll
-                    for (int p1 = 0; p1 < NP_I; ++p1)
-#pragma unroll
-                        for (int p2 = 0; p2 < NP_J; ++p2) {
-                            bad |= !isfinite(acc[p1][p2]);
-                            tl[p1 * WS + p2] = acc[p1][p2];
-                        }
-                }
-                __syncthreads();
-                const int colj = comp_offset(PROB, N, J) + ma * CW;
-                // mirrored rows start after the diagonal slab m2 == m1 of block (I,I)
-                const int cmir = (J == I && ma == m2lo) ? CW : 0;
-                double *drow = obase + (int64_t)rowbase * NDOF + colj;
-                const bool d16 = (NDOF % 2 == 0) && (W % 2 == 0) &&
-                                 ((reinterpret_cast<uintptr_t>(drow) & 15u) == 0);
-                // the element index x = tid + i*nthreads of an (r, c) grid of
-                // width wd is walked incrementally: one division per thread
-                // and phase instead of one per stored element
-                if (d16) {
-                    const int hw = W / 2, dr = nthreads / hw, dc = nthreads - dr * hw;
-                    int r = tid / hw, h = tid - r * hw;
-                    while (r < NR) {
-                        const int c = 2 * h;
-                        // two 8-byte LDS reads (rows are only 8-byte aligned)
-                        *reinterpret_cast<double2 *>(drow + (int64_t)r * NDOF + c) =
-                            make_double2(smem[r * WS + c], smem[r * WS + c + 1]);
-                        r += dr;
-                        h += dc;
-                        if (h >= hw) {
-                            h -= hw;
-                            ++r;
-                        }
-                    }
-                } else {
-                    const int dr = nthreads / W, dc = nthreads - dr * W;
-                    int r = tid / W, c = tid - r * W;
-                    while (r < NR) {
-                        drow[(int64_t)r * NDOF + c] = smem[r * WS + c];
-                        r += dr;
-                        c += dc;
-                        if (c >= W) {
-                            c -= W;
-                            ++r;
-                        }
-                    }
-                }
-                // mirror: tile column c is output row colj + c, holding the NR
-                // contiguous values of columns rowbase + r
-                double *mrow = obase + (int64_t)colj * NDOF + rowbase;
-                const int nc = W - cmir;
-                const bool m16 = (NDOF % 2 == 0) && (NR % 2 == 0) &&
-                                 ((reinterpret_cast<uintptr_t>(mrow) & 15u) == 0);
-                if (m16) {
-                    const int hr = NR / 2, dq = nthreads / hr, dh = nthreads - dq * hr;
-                    int q = tid / hr, h = tid - q * hr;  // tile column cmir + q, row pair h
-                    while (q < nc) {
-                        const int c = cmir + q, r = 2 * h;
-                        *reinterpret_cast<double2 *>(mrow + (int64_t)c * NDOF + r) =
-                            make_double2(smem[r * WS + c], smem[(r + 1) * WS + c]);
-                        q += dq;
-                        h += dh;
-                        if (h >= hr) {
-                            h -= hr;
-                            ++q;
-                        }
-                    }
-                } else {
-                    const int dq = nthreads / NR, dh = nthreads - dq * NR;
-                    int q = tid / NR, r = tid - q * NR;
-                    while (q < nc) {
-                        const int c = cmir + q;
-                        mrow[(int64_t)c * NDOF + r] = smem[r * WS + c];
-                        q += dq;
-                        r += dh;
-                        if (r >= NR) {
-                            r -= NR;
-                            ++q;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-    });
-    if (__syncthreads_or(bad) && tid == 0) atomicOr(status + e, P2S_STATUS_NONFINITE_BIT);
-}
-
-// One launch per column block (I, J >= I): each kernel holds the code of a
-// single block, which keeps it within the instruction cache (a kernel with
-// all three column blocks of I = 0 missed in it two orders of magnitude more
-// often than one with a single block).
-template <int PROB, int N, int I, int J>
-__global__ __launch_bounds__((CS<PROB, N, I, J, J + 1>::THREADS), (N <= 6 ? 3 : 2)) void k_contract(
-    const ElemDesc *__restrict__ desc, const int32_t *__restrict__ elist, int64_t e0, int64_t nitems,
-    int64_t padded, const double *__restrict__ tab, const double *__restrict__ mom,
-    double *__restrict__ out, uint32_t *__restrict__ status, double sK, double sM)
-{
-    using S = CS<PROB, N, I, J, J + 1>;
-    const int64_t item = xcd_remap(blockIdx.x, padded);
-    if (item >= nitems) return;
-    const int64_t eidx = e0 + item / S::NM_I;
-    const int64_t e = elist ? (int64_t)elist[eidx] : eidx;
-    const int m1 = (int)(item % S::NM_I);
-    const ElemDesc d = desc[e];
-    __shared__ __attribute__((aligned(16))) double smem[S::BUF];
-    contract_item<PROB, N, I, J, J + 1>(d, e, m1, tab, mom, out, status, sK, sM, smem, S::THREADS);
-}
-
-template <int PROB, int N, int I, int J>
-static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,
-                              const double *tab, const double *mom, double *out, uint32_t *status,
-                              double sK, double sM, hipStream_t st)
-{
-    using S = CS<PROB, N, I, J, J + 1>;
-    const int64_t nitems = count * S::NM_I;
-    const int64_t padded = (nitems + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_contract<PROB, N, I, J>), dim3((unsigned)padded), dim3(S::THREADS), 0, st, desc,
-                       elist, e0, nitems, padded, tab, mom, out, status, sK, sM);
-}
 
 // ---------------------------------------------------------------------------
 // Persistent schedule for batches of mixed orders: one launch of a fixed
@@ -514,21 +77,6 @@ int launch_contract_persistent(int problem, const ElemDesc *desc, const WorkItem
     return 0;
 }
 
-template <int PROB, int N>
-static void launch_contract_t(const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,
-                              const double *tab, const double *mom, double *out, uint32_t *status,
-                              double sK, double sM, hipStream_t st)
-{
-    launch_contract_i<PROB, N, 0, 0>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
-    if constexpr (PROB == 1) {
-        launch_contract_i<PROB, N, 0, 1>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
-        launch_contract_i<PROB, N, 0, 2>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
-        launch_contract_i<PROB, N, 1, 1>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
-        launch_contract_i<PROB, N, 1, 2>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
-        launch_contract_i<PROB, N, 2, 2>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
-    }
-}
-
 int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0,
                     int64_t count, const double *tab, const double *mom, double *out, uint32_t *status,
                     double sK, double sM, hipStream_t st)
@@ -546,3 +94,4 @@ int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *eli
 }
 
 }  // namespace p2s
+

@@ -107,7 +107,12 @@ constexpr int TAB_BASIS = TAB_PACK + PACKED_SIZE;
 // tailw[Q][j][a] = (2d+1)/2 w_a L_d(x_a), d = Q-1-j (zero when d < 0).
 constexpr int TAILW_STRIDE_Q = 4 * MAXQ;
 constexpr int TAB_TAILW = TAB_BASIS + (MAXQ + 1) * BASIS_STRIDE_Q;
-constexpr int TAB_SIZE = TAB_TAILW + (MAXQ + 1) * TAILW_STRIDE_Q;
+// Point tables of the sum-factorized direct quadrature: for order N and the
+// 2N-point Gauss rule, pt[N][t][m1][m2][a] = w_a X_m1(x_a) Y_m2(x_a) (type
+// t = 3X+Y), in the [t][m1][m2][.] layout of the linearization table.
+constexpr int PT_STRIDE_N = NTYPE * MAXN * MAXN * KPAD;
+constexpr int TAB_PT = TAB_TAILW + (MAXQ + 1) * TAILW_STRIDE_Q;
+constexpr int TAB_SIZE = TAB_PT + (MAXN + 1) * PT_STRIDE_N;
 // Per (element, field) tail record written by the moment stage in learned
 // mode: env[axis][j] at axis*4+j (axis 0 = u, 1 = v, 2 = w), the scale of
 // the tensor the axis was examined on at 12+axis.

@@ -17,7 +17,7 @@ struct MomentShape {
     int maxQu = 0, maxQuv = 0; // vector-unit form (rules of at most 16 points)
     int maxQw = 0, maxQvw = 0; // matrix-core form
 };
-size_t moments_smem_bytes(int maxN, int maxQw, int maxQvw);
+size_t moments_smem_bytes(int maxN, int maxQw, int maxQvw, bool tail = false);
 size_t moments_lds_bytes(const MomentShape &m);  // of the form launch_moments picks without tail records
 
 // `only` (may be null): elements with only[e] == 0 are skipped; with it the
@@ -35,6 +35,12 @@ void launch_moments(int problem, const MomentShape &m, const ElemDesc *desc, int
 int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0,
                     int64_t count, const double *tab, const double *mom, double *out, uint32_t *status,
                     double sK, double sM, hipStream_t st);
+
+// Sum-factorized direct quadrature (p2s_direct_sf.hip): the contraction's
+// three stages over the coupling samples alpha (rules of 2N points per axis).
+int launch_contract_dsf(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,
+                        const double *tab, const double *alpha, double *out, uint32_t *status, double sK, double sM,
+                        hipStream_t st);
 
 // One launch over a cost-sorted work list (scalar problem, mixed orders).
 int launch_contract_persistent(int problem, const ElemDesc *desc, const WorkItem *items, int64_t nitems,

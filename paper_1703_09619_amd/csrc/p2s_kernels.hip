@@ -223,13 +223,19 @@ __global__ __launch_bounds__(256) void k_coupling(const ElemDesc *__restrict__ d
 // tiles of 16, with the summed index in steps of 4.  One workgroup (4 waves)
 // per (element, field); the waves take the N tiles in turn.
 //
-// TAIL (learned order, K + 4 <= 16): rows K..K+3 of a pass whose axis is
-// sampled below the full rule MLP_KMAX hold the discrete Legendre
-// coefficients of the four highest degrees its rule resolves, on every line
-// it contracts (u on the samples, v on the u-moments, w on the (u,v)-
-// moments); the pass keeps their largest magnitudes and the largest
-// magnitude of the tensor it reads, and the workgroup writes them as the
-// (element, field) tail record (zeros for full axes).
+// TAIL (learned order, K + 4 <= 16): the tail statistic of every axis
+// sampled below the full rule MLP_KMAX.  Rows K..K+3 of that axis's pass
+// hold the discrete Legendre coefficients of the four highest degrees its
+// rule resolves (tail weights), and they are carried through the later
+// passes like moment rows, so that each axis's coefficients end up
+// projected onto the moment degrees of the other two axes:
+//   u tail rows: P1 rows K..K+3, through passes 2 and 3 -> T_u[j][l][q]
+//   v tail rows: P2 columns K..K+3 of l, through pass 3 -> T_v[k][j][q]
+//   w tail rows: pass 3 rows K..K+3                      -> T_w[k][l][j]
+// The workgroup keeps the largest magnitude of each T_x[j] and of the
+// moment tensor and writes them as the (element, field) tail record (zeros
+// for axes at the full rule).  The values do not depend on the order in
+// which the axes are contracted.
 //
 // FP64 MFMA 16x16x4 lane layout (wave64): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; result register i of lane l is D[4i + l/16][l%16].
@@ -268,15 +274,18 @@ __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const d
     const int L = Qv * Qw, P = Qu * L;
     const int QWS = Qw | 1;  // odd row stride of P2
     const double *A = alpha + d.alpha_off + (int64_t)f * P;
-    double *P1 = sm;          // [K][Qv*Qw]    (k; b, c)
-    double *P2 = sm + p2off;  // [K][K][QWS]   (k, l; c)
+    double *P1 = sm;          // [K1][Qv*Qw]   (k; b, c)
+    double *P2 = sm + p2off;  // [K1][K2][QWS] (k, l; c)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     const int r16 = lane & 15, k4 = lane >> 4;
     double rec[TAIL_REC];
 #pragma unroll
     for (int i = 0; i < TAIL_REC; ++i) rec[i] = 0.0;
-    // workgroup-uniform: which axes take the tail statistic
+    // workgroup-uniform: which axes take the tail statistic; K1 rows of P1
+    // (u moments, then u tail rows), K2 rows l' of P2 (v moments, then v
+    // tail rows)
     const bool tu = TAIL && Qu < MLP_KMAX, tv = TAIL && Qv < MLP_KMAX, tw = TAIL && Qw < MLP_KMAX;
+    const int K1 = K + (tu ? 4 : 0), K2 = K + (tv ? 4 : 0);
     double wa[MAXQ / 4];  // operand A of the current pass, one value per step of 4
 
     // pass 1: contract u; columns (b,c).  A wave takes TG consecutive column
@@ -302,25 +311,19 @@ __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const d
             const int col = (nt0 + t) * 16 + r16;
             d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int ks = 0; ks < MAXQ / 4; ++ks) {
-                if (ks < su) {
-                    if (tu) rec[12] = fmax(rec[12], fabs(xs[t][ks]));
-                    acc = mfma64(wa[ks], xs[t][ks], acc);
-                }
-            }
+            for (int ks = 0; ks < MAXQ / 4; ++ks)
+                if (ks < su) acc = mfma64(wa[ks], xs[t][ks], acc);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int m = 4 * i + k4;
-                if (col < L) {
-                    if (m < K) P1[m * L + col] = acc[i];
-                    else if (tu && m < K + 4) rec[m - K] = fmax(rec[m - K], fabs(acc[i]));
-                }
+                if (col < L && m < K1) P1[m * L + col] = acc[i];
             }
         }
     }
     __syncthreads();
-    // pass 2: contract v; columns n = (k, c)
-    const int sv = (Qv + 3) >> 2, n2 = K * Qw;
+    // pass 2: contract v; columns n = (k, c), k < K1 (moment rows, then the
+    // u tail rows when u is reduced)
+    const int sv = (Qv + 3) >> 2, n2 = K1 * Qw;
 #pragma unroll
     for (int ks = 0; ks < MAXQ / 4; ++ks) wa[ks] = ks < sv ? pass_weight(tab, Qv, K, tv, r16, 4 * ks + k4) : 0.0;
     for (int nt = wave; nt * 16 < n2; nt += nwave) {
@@ -335,19 +338,12 @@ __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const d
         }
         d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ks = 0; ks < MAXQ / 4; ++ks) {
-            if (ks < sv) {
-                if (tv) rec[13] = fmax(rec[13], fabs(xv[ks]));
-                acc = mfma64(wa[ks], xv[ks], acc);
-            }
-        }
+        for (int ks = 0; ks < MAXQ / 4; ++ks)
+            if (ks < sv) acc = mfma64(wa[ks], xv[ks], acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int m = 4 * i + k4;
-            if (n < n2) {
-                if (m < K) P2[(k * K + m) * QWS + c] = acc[i];
-                else if (tv && m < K + 4) rec[4 + m - K] = fmax(rec[4 + m - K], fabs(acc[i]));
-            }
+            if (n < n2 && m < K2) P2[(k * K2 + m) * QWS + c] = acc[i];
         }
     }
     __syncthreads();
@@ -356,8 +352,8 @@ __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const d
     // pass 2) when K^3 doubles fit below P2, else after P2 (the buffer is
     // sized for that case)
     double *I = mom + d.mom_off + (int64_t)f * K * K * K;
-    double *Is = (K * K * K <= p2off) ? sm : P2 + K * K * QWS;
-    const int sw = (Qw + 3) >> 2, n3 = K * K;
+    double *Is = (K * K * K <= p2off) ? sm : P2 + K1 * K2 * QWS;
+    const int sw = (Qw + 3) >> 2, n3 = K1 * K2;
 #pragma unroll
     for (int ks = 0; ks < MAXQ / 4; ++ks) wa[ks] = ks < sw ? pass_weight(tab, Qw, K, tw, r16, 4 * ks + k4) : 0.0;
     for (int nt = wave; nt * 16 < n3; nt += nwave) {
@@ -370,18 +366,27 @@ __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const d
         }
         d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ks = 0; ks < MAXQ / 4; ++ks) {
-            if (ks < sw) {
-                if (tw) rec[14] = fmax(rec[14], fabs(xw[ks]));
-                acc = mfma64(wa[ks], xw[ks], acc);
-            }
-        }
+        for (int ks = 0; ks < MAXQ / 4; ++ks)
+            if (ks < sw) acc = mfma64(wa[ks], xw[ks], acc);
+        // column n = (k', l'): k' >= K is a u tail row, l' >= K a v tail row
+        const int kk = n / K2, ll = n - (n / K2) * K2;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int m = 4 * i + k4;
-            if (n < n3) {
-                if (m < K) Is[n * K + m] = acc[i];
-                else if (tw && m < K + 4) rec[8 + m - K] = fmax(rec[8 + m - K], fabs(acc[i]));
+            if (n < n3 && m < K + (tw ? 4 : 0)) {
+                if (!TAIL) {
+                    Is[n * K + m] = acc[i];
+                } else if (kk < K && ll < K) {
+                    if (m < K) {
+                        Is[(kk * K + ll) * K + m] = acc[i];
+                        rec[12] = fmax(rec[12], fabs(acc[i]));
+                    } else {
+                        rec[8 + m - K] = fmax(rec[8 + m - K], fabs(acc[i]));  // T_w
+                    }
+                } else if (m < K) {
+                    if (kk >= K && ll < K) rec[kk - K] = fmax(rec[kk - K], fabs(acc[i]));         // T_u
+                    else if (kk < K && ll >= K) rec[4 + ll - K] = fmax(rec[4 + ll - K], fabs(acc[i]));  // T_v
+                }
             }
         }
     }
@@ -397,9 +402,12 @@ __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const d
         }
         __syncthreads();
         if (tid < 15) {
+            // scale of every reduced axis: the largest moment magnitude
+            const int src = tid >= 12 ? 12 : tid;
+            const bool on = tid < 12 || (tid == 12 && tu) || (tid == 13 && tv) || (tid == 14 && tw);
             double v = 0.0;
-            for (int w = 0; w < nwave; ++w) v = fmax(v, sm[w * TAIL_REC + tid]);
-            tailst[(e * F + f) * TAIL_REC + tid] = v;
+            for (int w = 0; w < nwave; ++w) v = fmax(v, sm[w * TAIL_REC + src]);
+            tailst[(e * F + f) * TAIL_REC + tid] = on ? v : 0.0;
         }
     }
 }
@@ -540,12 +548,14 @@ __global__ __launch_bounds__(256) void k_moments_valu(const ElemDesc *__restrict
 // P1 [K][Qv*Qw] followed by P2 [K][K][Qw | 1]; the staged K^3 tile of
 // pass 3 reuses P1 when it fits there, else follows P2; at least 4 waves x
 // TAIL_REC doubles (the tail-record reduction reuses the start).
-int moments_p2_offset(int maxN, int maxQvw) { return maxQvw * (2 * maxN - 1); }
-size_t moments_smem_bytes(int maxN, int maxQw, int maxQvw)
+// With tail records P1 and P2 carry four more rows per reduced axis: P1
+// [K+4][Qv*Qw], P2 [K+4][K+4][Qw | 1].
+int moments_p2_offset(int maxN, int maxQvw, bool tail) { return maxQvw * (2 * maxN - 1 + (tail ? 4 : 0)); }
+size_t moments_smem_bytes(int maxN, int maxQw, int maxQvw, bool tail)
 {
-    const int K = 2 * maxN - 1;
-    const size_t p2 = (size_t)moments_p2_offset(maxN, maxQvw);
-    size_t n = p2 + (size_t)(K * K * (maxQw | 1));
+    const int K = 2 * maxN - 1, K4 = K + (tail ? 4 : 0);
+    const size_t p2 = (size_t)moments_p2_offset(maxN, maxQvw, tail);
+    size_t n = p2 + (size_t)(K4 * K4 * (maxQw | 1));
     if ((size_t)(K * K * K) > p2) n += (size_t)(K * K * K);
     return sizeof(double) * (n > 4 * TAIL_REC ? n : 4 * TAIL_REC);
 }
@@ -561,7 +571,7 @@ static size_t valu_smem_bytes(int maxN, int maxQu, int maxQuv, int maxQw)
 size_t moments_lds_bytes(const MomentShape &m)
 {
     return m.maxQ <= SPLIT_MAXQ ? valu_smem_bytes(m.maxN, m.maxQu, m.maxQuv, m.maxQw)
-                                : moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw);
+                                : moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -618,16 +628,16 @@ void launch_moments(int problem, const MomentShape &m, const ElemDesc *desc, int
     const int F = num_fields(problem);
     if (tailst)
         hipLaunchKernelGGL(k_moments<true>, dim3((unsigned)count, F), dim3(256),
-                           moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw), st, desc, e0, F, alpha, tab, mom,
-                           moments_p2_offset(m.maxN, m.maxQvw), only, tailst, elist);
+                           moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw, true), st, desc, e0, F, alpha, tab, mom,
+                           moments_p2_offset(m.maxN, m.maxQvw, true), only, tailst, elist);
     else if (m.maxQ <= SPLIT_MAXQ)
         hipLaunchKernelGGL(k_moments_valu, dim3((unsigned)count, F), dim3(256),
                            valu_smem_bytes(m.maxN, m.maxQu, m.maxQuv, m.maxQw), st, desc, e0, alpha, tab, mom,
                            valu_p2_offset(m.maxN, m.maxQuv), only, elist);
     else
         hipLaunchKernelGGL(k_moments<false>, dim3((unsigned)count, F), dim3(256),
-                           moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw), st, desc, e0, F, alpha, tab, mom,
-                           moments_p2_offset(m.maxN, m.maxQvw), only, tailst, elist);
+                           moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw, false), st, desc, e0, F, alpha, tab, mom,
+                           moments_p2_offset(m.maxN, m.maxQvw, false), only, tailst, elist);
 }
 
 int prepare_kernels()

@@ -14,6 +14,8 @@
 // softmax cross-entropy backward, weight gradients, Adam).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "p2s_internal.h"
 #include "p2s_kernels.h"
 
@@ -132,14 +134,18 @@ __global__ void k_sum(int64_t n, const float *__restrict__ x, float *__restrict_
     if (threadIdx.x == 0) *out = s[0];
 }
 
+// omb1 = 1 - b1, omb2 = 1 - b2, c1 = 1 - b1^t, c2 = 1 - b2^t are formed in
+// FP64 on the host: in FP32, 1 - 0.999f and 1 - 0.999f^t lose up to five
+// digits to cancellation.
 __global__ void k_adam(int P, float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
-                       float *__restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2)
+                       float *__restrict__ v, float lr, float b1, float b2, float omb1, float omb2, float eps,
+                       float c1, float c2)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= P) return;
     const float gt = g[t];
-    const float mt = b1 * m[t] + (1.f - b1) * gt;
-    const float vt = b2 * v[t] + (1.f - b2) * gt * gt;
+    const float mt = b1 * m[t] + omb1 * gt;
+    const float vt = b2 * v[t] + omb2 * gt * gt;
     m[t] = mt;
     v[t] = vt;
     p[t] -= lr * (mt / c1) / (sqrtf(vt / c2) + eps);
@@ -186,9 +192,9 @@ __global__ void k_choose(int64_t E, const float *__restrict__ Z, float p_cover, 
 // is exact unless the integrand has Legendre content along that axis at
 // degrees >= 2Q - k; the highest moment degree is K_m - 1 = 2N - 2.  The
 // moment stage records, per field and axis, the envelope A_j (largest
-// magnitude over the lines it contracts) of the discrete Legendre
-// coefficients of degrees Q-1 .. Q-4 and the scale S (largest magnitude of
-// the tensor those lines come from).  Per axis, over the fields:
+// magnitude) of the discrete Legendre coefficients of degrees Q-1 .. Q-4
+// along the axis, projected on the other two axes onto the moment degrees,
+// and the scale S (largest moment magnitude).  Per axis, over the fields:
 //   r2  = min(1, max(A_1/A_3, A_2/A_4))    (decay over two degrees)
 //   est = max(A_1, A_2) r2^((Q - K_m + 2)/2)  (content at degree 2Q-K_m+1)
 //   t   = est / S.
@@ -305,10 +311,10 @@ void launch_mlp_backward(int64_t B, const float *params, const float *X, const f
 
 void launch_adam(float *params, const float *grad, float *m, float *v, float lr, int step, hipStream_t st)
 {
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-    hipLaunchKernelGGL(k_adam, dim3(nblk(MLP_PARAMS, 256)), dim3(256), 0, st, MLP_PARAMS, params, grad, m, v, lr, b1,
-                       b2, 1e-8f, c1, c2);
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - std::pow(b1, step)), c2 = (float)(1.0 - std::pow(b2, step));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(MLP_PARAMS, 256)), dim3(256), 0, st, MLP_PARAMS, params, grad, m, v, lr,
+                       (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, c1, c2);
 }
 
 void launch_choose(int64_t E, const float *Z, float p_cover, int k_direct, int32_t *quad, ElemDesc *desc,

@@ -171,6 +171,18 @@ void build_tables(double *tab)
             for (int k = 0; k < KPAD; ++k)
                 tab[TAB_LEGW + Q * LEGW_STRIDE_Q + k * MAXQ + a] = w[a] * L[k];
         }
+        if (Q % 2 == 0 && Q / 2 >= 2 && Q / 2 <= MAXN) {
+            const int N = Q / 2;
+            const double *bas = tab + TAB_BASIS + Q * BASIS_STRIDE_Q;
+            for (int X = 0; X < NFAM; ++X)
+                for (int Y = 0; Y < NFAM; ++Y)
+                    for (int m1 = 0; m1 < fam_dim(X, N); ++m1)
+                        for (int m2 = 0; m2 < fam_dim(Y, N); ++m2)
+                            for (int a = 0; a < Q; ++a)
+                                tab[TAB_PT + N * PT_STRIDE_N + (3 * X + Y) * LIN_STRIDE_T + m1 * LIN_STRIDE_M1 +
+                                    m2 * KPAD + a] = w[a] * bas[(X * MAXN + m1) * MAXQ + a] *
+                                                     bas[(Y * MAXN + m2) * MAXQ + a];
+        }
         double LL[MAXQ];
         for (int a = 0; a < Q; ++a) {
             legendre_values(Q - 1, x[a], LL);

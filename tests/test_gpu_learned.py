@@ -93,31 +93,33 @@ def test_adam_step_matches_reference(env):
 
 
 def test_adam_six_steps_match_reference(env):
-    """Six training steps on one batch against six steps of the FP64
-    reference (gradient + Adam with bias correction at steps 1..6, the
-    reference's Adam pinned by the constant-gradient closed form)."""
+    """Six training steps: before each, the GPU gradient at the GPU's
+    current parameters is read; the FP64 reference Adam (pinned by the
+    constant-gradient closed form) applied to those gradients, with bias
+    correction at steps 1..6, must give the GPU's parameters after the step.
+    (The gradient kernels are checked against the reference separately.)"""
     torch, mlp, ctx = env["torch"], env["mlp"], env["ctx"]
     ctx.mlp_init(seed=9, max_batch=512)
-    p = ctx.mlp_params().astype(np.float64)
     rng = np.random.default_rng(12)
     x = rng.standard_normal((128, 85)).astype(np.float32)
     y = rng.integers(0, 19, size=(128, 3)).astype(np.int32)
     xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    p = ctx.mlp_params().astype(np.float64)
     m, v = np.zeros_like(p), np.zeros_like(p)
     lr = 1e-3
-    gmin = np.full_like(p, np.inf)
     for t in range(1, 7):
-        _, g = mlp.loss_and_grad(p, x.astype(np.float64), y)
-        gmin = np.minimum(gmin, np.abs(g))
-        p, m, v = mlp.adam(p, g, m, v, t, lr)
+        _, g = ctx.mlp_gradients(xd, yd)
+        g = g.cpu().numpy().astype(np.float64)
+        pr, m, v = mlp.adam(p, g, m, v, t, lr)
         ctx.mlp_train_step(xd, yd, lr, loss)
-    pg = ctx.mlp_params().astype(np.float64)
-    # parameters whose gradient stayed away from zero (elsewhere the FP32
-    # direction g/|g| is not determined by the data)
-    big = gmin > 1e-4
-    assert big.sum() > 1000
-    assert np.abs(pg - p)[big].max() <= 2e-6
+        p = ctx.mlp_params().astype(np.float64)
+        # FP32 parameters and moment arithmetic: a few ulps of |p| plus
+        # single-precision rounding of the step (relative ~1e-6)
+        tol = 4e-7 * np.abs(pr) + 2e-6 * lr
+        live = np.abs(g) > 1e-6  # the step of a vanishing gradient is g/(|g| + eps)-sensitive
+        assert live.sum() > 20000, t
+        assert (np.abs(p - pr)[live] <= tol[live]).all(), (t, np.abs(p - pr)[live].max())
 
 
 def test_predict_matches_reference_choice(env):
@@ -244,9 +246,12 @@ def test_trained_model_accuracy_and_gain(env):
 
 
 def test_tail_records_and_decision_match_oracle(env):
-    """Tail records of the moment stage and the element tail values against
-    the FP64 reference computed from the oracle's own coupling samples; the
-    fallback decision follows tau > theta element by element."""
+    """Tail records of the moment stage against the FP64 reference of the
+    statistic's definition (oracle/tail.py) evaluated on the oracle's own
+    coupling samples; then, in a learned execution, the element tail values
+    against the reference's, and each fallback decision against the
+    reference's tau > theta, with theta placed in a gap of the reference's
+    tau values much wider than their rounding."""
     torch, W, ctx, oracle, p2s = env["torch"], env["W"], env["ctx"], env["oracle"], env["p2s"]
     from oracle import tail
     w = W.make("scalar_planewave", E=6, seed=W.BASE_SEED + 7)
@@ -256,16 +261,12 @@ def test_tail_records_and_decision_match_oracle(env):
     for e in range(w.E):
         a = oracle.coupling(w.problem, w.material, w.mat[e], w.nodes[e], *rules[e])
         ref = tail.records(a, *rules[e], int(w.orders[e]))
-        scale = ref[:, 12:15].max(0)  # per-axis tensor scale
-        for ax in range(3):
-            cols = list(range(4 * ax, 4 * ax + 4)) + [12 + ax]
-            d = np.abs(rec[e][:, cols] - ref[:, cols]).max()
-            assert d <= 1e-13 * max(scale[ax], 1e-300) + 1e-12 * np.abs(ref[:, cols]).max(), (e, ax, d)
-    # learned execution with an untrained network: tail values and decisions.
-    # The tail value combines the top-degree coefficients, which are small
-    # differences of O(1) samples; the records above agree to ~1e-13 of each
-    # tensor's scale, so tau is compared with the oracle's only loosely, and
-    # exactly with the reference formula applied to the GPU's own records.
+        S = ref[:, 12:15].max()
+        d = np.abs(rec[e] - ref).max()
+        print("element", e, "rules", rules[e].tolist(), "max record diff %.3e of scale %.3e" % (d, S), flush=True)
+        assert d <= 1e-13 * S, (e, d, S)
+        assert ((rec[e] == 0) == (ref == 0)).all()  # axes at the full rule record nothing
+    # learned execution with an untrained network (reduced rules on most axes)
     ctx.mlp_init(seed=21, max_batch=512)
     w = W.make("scalar_planewave", E=24, seed=W.BASE_SEED + 8)
     nodes, mat = torch.from_numpy(w.nodes).cuda(), torch.from_numpy(w.mat).cuda()
@@ -275,21 +276,21 @@ def test_tail_records_and_decision_match_oracle(env):
     pl.execute(nodes, mat)
     chosen = pl.rules()
     tau = pl.tail_values()
-    rec_gpu = ctx.plan(w.problem, w.material, w.orders, chosen).tail_records(nodes, mat).cpu().numpy()
-    tau_formula = np.array([tail.tail_value(rec_gpu[e], chosen[e], 6) for e in range(w.E)])
-    assert np.allclose(tau, tau_formula, rtol=1e-12, atol=0.0)
     ref_tau = np.array([tail.tail_value(tail.records(
         oracle.coupling(w.problem, w.material, w.mat[e], w.nodes[e], *chosen[e]), *chosen[e], 6), chosen[e], 6)
         for e in range(w.E)])
-    print("tau vs oracle: max rel diff %.3e" % np.max(np.abs(tau - ref_tau) / np.maximum(ref_tau, 1e-300)), flush=True)
-    assert np.allclose(tau, ref_tau, rtol=1e-4, atol=1e-12)
-    # threshold in the widest gap between consecutive values near the median
-    srt = np.sort(tau[tau > 0])
-    mid = len(srt) // 2
-    j = max(range(max(1, mid - 3), min(len(srt), mid + 4)), key=lambda i: srt[i] / srt[i - 1])
+    assert (ref_tau > 0).sum() >= 12
+    rel = np.abs(tau - ref_tau) / np.maximum(ref_tau, 1e-300)
+    print("tau vs reference: max rel diff %.3e" % rel.max(), flush=True)
+    assert rel.max() <= 1e-6
+    # theta in the widest (log) gap between consecutive reference values
+    srt = np.sort(ref_tau[ref_tau > 0])
+    j = max(range(1, len(srt)), key=lambda i: srt[i] / srt[i - 1])
+    assert srt[j] / srt[j - 1] > 1.01  # gap >> rounding of tau (1e-6 above)
     theta = float(np.sqrt(srt[j - 1] * srt[j]))
     pl.set_learned(True, 0.3, theta)
     _, st = pl.execute(nodes, mat)
     back = (st.cpu().numpy() & p2s.STATUS_FALLBACK) != 0
-    assert (back == (tau > theta)).all()
+    assert (back == (ref_tau > theta)).all()
+    assert back.any() and (~back).any()
     assert (pl.rules()[back] == 24).all() and (pl.rules()[~back] == chosen[~back]).all()

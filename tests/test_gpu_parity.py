@@ -453,3 +453,35 @@ def test_nonfinite_status(env):
         out, off, st, _ = gpu_fill(env, w)
         assert st[0] == 0 and st[2] == 0
         assert st[1] & p2s.STATUS_NONFINITE and st[3] & p2s.STATUS_NONFINITE
+
+
+@pytest.mark.parametrize("problem,N,E", [(0, 2, 3), (0, 3, 3), (0, 5, 2), (0, 7, 1), (0, 8, 1),
+                                         (1, 2, 2), (1, 3, 2), (1, 4, 2), (1, 5, 1), (1, 7, 1), (1, 8, 1)])
+def test_direct_sf_orders(env, problem, N, E):
+    """Sum-factorized direct quadrature (rules of 2N points per axis)
+    against the oracle, every order of both problems."""
+    w = make_small(env, problem, N, E, (2 * N, 2 * N, 2 * N), seed=500 + 10 * problem + N)
+    check_against_oracle(env, w, method=2)
+
+
+def test_direct_sf_workloads(env):
+    """Sum-factorized direct quadrature on the scalar N=4 workload (all 64
+    elements, 8^3 points) and a subset of the vector N=6 workload (12^3
+    points), against the oracle; and on mixed orders (Q = 2N) with the
+    stiffness and mass weights changed."""
+    W = env["W"]
+    check_against_oracle(env, W.make("scalar_n4"), method=2)
+    check_against_oracle(env, W.subset(W.make("vector_n6", E=16), np.arange(5)), method=2)
+    w = W.make("scalar_mixed", E=200)
+    idx = []
+    for N in range(2, 9):
+        idx += list(np.nonzero(w["orders"] == N)[0][:1])
+    check_against_oracle(env, W.subset(w, np.array(sorted(idx))), sK=0.7, sM=-1.3, method=2)
+
+
+def test_direct_sf_rule_restriction(env):
+    p2s, ctx = env["p2s"], env["ctx"]
+    with pytest.raises(p2s.P2SError, match="2N Gauss points"):
+        ctx.plan(0, 0, [4], [[8, 8, 7]], method=p2s.METHOD_DIRECT_SF)
+    with pytest.raises(p2s.P2SError, match="FP64"):
+        ctx.plan(1, 1, [4], [[8, 8, 8]], method=p2s.METHOD_DIRECT_SF, precision=p2s.SPLIT_FP32)
