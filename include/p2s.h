@@ -294,6 +294,26 @@ int p2s_fill_element_matrices(p2s_ctx ctx, const p2s_terms *terms, int64_t E,
                               const int32_t *orders, const int32_t *quad,
                               double *out, uint32_t *status, void *stream);
 
+/* Allocation-free fill, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same fill as p2s_fill_element_matrices (FP64
+ * product-to-sum only) for E elements of one order N and one rule
+ * (Qu, Qv, Qw); nodes, material, out, status [device] as in
+ * p2s_plan_execute, out laid out as E blocks of p2s_num_dofs(N)^2 doubles.
+ * Its workspace (descriptors, coupling samples, moments) is a fixed 64 MiB
+ * device array that the library holds on each GPU for the life of the
+ * process; the elements go through it in chunks, one chunk after another on
+ * `stream`.  Nothing is allocated and nothing is copied from the host: the
+ * call only enqueues kernels.  Every call on a GPU shares that GPU's array,
+ * so calls that overlap on one GPU (other streams, other host threads)
+ * race and must be serialized by the caller.  Errors: P2S_EORDER,
+ * P2S_EQUAD (points outside 1..P2S_MAX_Q or a rule the moment stage cannot
+ * hold), P2S_EINVAL (other precision or method, bad enums, NULL buffers, or
+ * an element whose workspace alone exceeds the 64 MiB). */
+int p2s_fill_uniform_noalloc(p2s_ctx ctx, const p2s_terms *terms, int64_t E, int N,
+                             int Qu, int Qv, int Qw, const double *nodes, const double *material,
+                             double *out, uint32_t *status, void *stream);
+
 /* Stage outputs, for verification of each step against its definition.
  * Coupling samples: alpha [device][E][F][Qu*Qv*Qw] (unweighted, packed
  * field order of P2S_ALPHA_SAMPLED).  Moments: [device][E][F][K][K][K],

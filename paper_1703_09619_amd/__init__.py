@@ -37,7 +37,7 @@ EXPORTS = (
     "p2s_plan_replay", "p2s_mlp_init", "p2s_mlp_set_params", "p2s_mlp_get_params", "p2s_mlp_save",
     "p2s_mlp_load", "p2s_features", "p2s_mlp_forward", "p2s_mlp_gradients", "p2s_mlp_train_step",
     "p2s_mlp_predict", "p2s_plan_set_learned", "p2s_plan_rules", "p2s_rel_error", "p2s_plan_tail_values",
-    "p2s_plan_tail_records",
+    "p2s_plan_tail_records", "p2s_fill_uniform_noalloc",
 )
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 85, 128, 57, 34873
 KMIN, KMAX = 6, 24
@@ -79,6 +79,8 @@ def load():
         lib.p2s_plan_destroy.argtypes = [vp]
         lib.p2s_plan_destroy.restype = None
         lib.p2s_fill_element_matrices.argtypes = [vp, ctypes.POINTER(_Terms), i64, vp, vp, vp, vp, vp, vp, vp]
+        lib.p2s_fill_uniform_noalloc.argtypes = [vp, ctypes.POINTER(_Terms), i64, i32, i32, i32, i32, vp, vp, vp,
+                                                 vp, vp]
         lib.p2s_plan_coupling.argtypes = [vp, vp, vp, vp, vp]
         lib.p2s_plan_moments.argtypes = [vp, vp, vp, vp, vp]
         lib.p2s_plan_profile.argtypes = [vp, i32]
@@ -112,7 +114,8 @@ def load():
                   "p2s_plan_replay", "p2s_mlp_init", "p2s_mlp_set_params", "p2s_mlp_get_params",
                   "p2s_mlp_save", "p2s_mlp_load", "p2s_features", "p2s_mlp_forward", "p2s_mlp_gradients",
                   "p2s_mlp_train_step", "p2s_mlp_predict", "p2s_plan_set_learned", "p2s_plan_rules",
-                  "p2s_rel_error", "p2s_plan_tail_values", "p2s_plan_tail_records"):
+                  "p2s_rel_error", "p2s_plan_tail_values", "p2s_plan_tail_records",
+                  "p2s_fill_uniform_noalloc"):
             getattr(lib, f).restype = i32
         _lib = lib
     return _lib
@@ -281,6 +284,18 @@ class Context:
                                               _stream(stream))
         self.check(rc, "p2s_fill_element_matrices")
         return out, status
+
+    def fill_uniform_noalloc(self, problem, material_kind, nodes, material, E, N, Q, out, status,
+                             stiff_scale=1.0, mass_scale=1.0, stream=None):
+        """p2s_fill_uniform_noalloc: E elements of order N and rule Q (3
+        points per axis) through the library's fixed device scratch; out and
+        status are caller-allocated device tensors."""
+        t = terms(problem, material_kind, FP64, METHOD_P2S, stiff_scale, mass_scale)
+        Qu, Qv, Qw = (int(q) for q in Q)
+        rc = load().p2s_fill_uniform_noalloc(self._h, ctypes.byref(t), int(E), int(N), Qu, Qv, Qw,
+                                             _dev_ptr(nodes), _dev_ptr(material), _dev_ptr(out),
+                                             _dev_ptr(status), _stream(stream))
+        self.check(rc, "p2s_fill_uniform_noalloc")
 
     def plan(self, problem, material, orders, quad, precision=FP64, method=METHOD_P2S,
              stiff_scale=1.0, mass_scale=1.0) -> "Plan":

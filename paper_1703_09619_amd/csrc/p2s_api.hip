@@ -37,8 +37,37 @@ struct p2s_ctx_s {
           *d_lossb = nullptr;
     // plans of p2s_fill_element_matrices, least recently used first
     std::vector<p2s_plan> fill_cache;
+    // device address of this GPU's `scratch` array
+    double *scratch = nullptr;
 };
 constexpr size_t FILL_CACHE_PLANS = 8;
+
+// Device scratch of p2s_fill_uniform_noalloc: descriptors, coupling samples
+// and moment tensors of one chunk of elements.  Each GPU the library runs
+// on holds its own copy for the life of the process.  Host code never uses
+// the array's name as an address: p2s_create looks up the device address
+// (hipGetSymbolAddress) and keeps it in the context.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+// Descriptors of `count` elements of one order and rule, element e's block
+// at e * ndof2 of the chunk's output and its samples and moments at e times
+// their per-element sizes in the scratch.
+__global__ void k_uniform_desc(ElemDesc *__restrict__ desc, int64_t count, int N, int Qu, int Qv, int Qw,
+                               int64_t ndof2, int64_t na, int64_t nm)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    ElemDesc d;
+    d.N = N;
+    d.Qu = Qu;
+    d.Qv = Qv;
+    d.Qw = Qw;
+    d.out_off = e * ndof2;
+    d.alpha_off = e * na;
+    d.mom_off = e * nm;
+    desc[e] = d;
+}
 
 struct Chunk {
     int64_t e0 = 0, count = 0;
@@ -208,6 +237,16 @@ int p2s_create(p2s_ctx *out, int device)
     if (hipMalloc(&ctx->d_tab32, sizeof(float) * T32_SIZE) != hipSuccess) {
         p2s_destroy(ctx);
         return fail(nullptr, P2S_ENOMEM, "p2s_create: table allocation failed");
+    }
+    {
+        // with the context's device current: this GPU's copy of the scratch
+        void *p = nullptr;
+        const hipError_t r = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (r != hipSuccess || !p) {
+            p2s_destroy(ctx);
+            return fail(nullptr, P2S_EHIP, "p2s_create: scratch symbol lookup failed: %s", hipGetErrorString(r));
+        }
+        ctx->scratch = static_cast<double *>(p);
     }
     if (hipMemcpy(ctx->d_tab, tab.data(), sizeof(double) * TAB_SIZE, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(ctx->d_tab32, tab32.data(), sizeof(float) * T32_SIZE, hipMemcpyHostToDevice) != hipSuccess ||
@@ -716,6 +755,78 @@ int p2s_fill_element_matrices(p2s_ctx ctx, const p2s_terms *terms, int64_t E, co
         ctx->fill_cache.push_back(plan);
     }
     return p2s_plan_execute(plan, nodes, material, out, status, stream);
+}
+
+int p2s_fill_uniform_noalloc(p2s_ctx ctx, const p2s_terms *terms, int64_t E, int N, int Qu, int Qv, int Qw,
+                             const double *nodes, const double *material, double *out, uint32_t *status,
+                             void *stream)
+{
+    if (!ctx) return P2S_EINVAL;
+    if (!terms) return fail(ctx, P2S_EINVAL, "noalloc: NULL terms");
+    const int problem = terms->problem, kind = terms->material;
+    if (problem != P2S_SCALAR && problem != P2S_VECTOR) return fail(ctx, P2S_EINVAL, "noalloc: bad problem %d", problem);
+    int stride = 0;
+    switch (kind) {
+    case P2S_MAT_SINCOSEXP: stride = 1; break;
+    case P2S_MAT_ROTDIAG: stride = 12; break;
+    case P2S_MAT_PLANEWAVE: stride = 4; break;
+    case P2S_ALPHA_SAMPLED: stride = 0; break;
+    default: return fail(ctx, P2S_EINVAL, "noalloc: bad material %d", kind);
+    }
+    if (problem == P2S_SCALAR && kind == P2S_MAT_ROTDIAG)
+        return fail(ctx, P2S_EINVAL, "noalloc: the scalar problem takes an isotropic material");
+    if (terms->method != P2S_METHOD_P2S || terms->precision != P2S_FP64)
+        return fail(ctx, P2S_EINVAL, "noalloc: FP64 product-to-sum only");
+    if (E < 0) return fail(ctx, P2S_EINVAL, "noalloc: negative E");
+    if (N < 2 || N > P2S_MAX_ORDER) return fail(ctx, P2S_EORDER, "noalloc: order %d (allowed 2..%d)", N, P2S_MAX_ORDER);
+    if (Qu < 1 || Qu > P2S_MAX_Q || Qv < 1 || Qv > P2S_MAX_Q || Qw < 1 || Qw > P2S_MAX_Q)
+        return fail(ctx, P2S_EQUAD, "noalloc: Gauss points per axis must be 1..%d", P2S_MAX_Q);
+    MomentShape ms;
+    ms.maxN = N;
+    ms.maxQ = std::max({Qu, Qv, Qw});
+    ms.maxQu = Qu;
+    ms.maxQuv = Qu * Qv;
+    ms.maxQw = Qw;
+    ms.maxQvw = Qv * Qw;
+    if (moments_lds_bytes(ms) > LDS_LIMIT || moments_smem_bytes(N, Qw, Qv * Qw) > LDS_LIMIT)
+        return fail(ctx, P2S_EQUAD, "noalloc: rule too large for the moment stage at order %d", N);
+    if (E == 0) return P2S_OK;
+    if (!material || !out || !status || (!nodes && kind != P2S_ALPHA_SAMPLED))
+        return fail(ctx, P2S_EINVAL, "noalloc: NULL buffer");
+    if (!ctx->scratch) return fail(ctx, P2S_EHIP, "noalloc: no scratch on this device");
+    const int F = num_fields(problem), K = 2 * N - 1;
+    const int64_t P = (int64_t)Qu * Qv * Qw;
+    const int64_t na = F * P, nm = (int64_t)F * K * K * K;
+    const int64_t nd = num_dofs(problem, N), ndof2 = nd * nd;
+    const int64_t mstride = kind == P2S_ALPHA_SAMPLED ? na : stride;
+    // scratch layout of a chunk of c elements: descriptors (rounded up to
+    // whole doubles), then c * na samples, then c * nm moments
+    const int64_t cap = (int64_t)(NOALLOC_SCRATCH_BYTES / sizeof(double));
+    const int64_t desc_d = (int64_t)((sizeof(ElemDesc) + sizeof(double) - 1) / sizeof(double));
+    const int64_t per = desc_d + na + nm;
+    const int64_t chunk = (cap - 64) / per;  // 64 doubles: alignment padding of two regions
+    if (chunk < 1)
+        return fail(ctx, P2S_EINVAL, "noalloc: one element needs %lld bytes of scratch, more than the %zu available",
+                    (long long)(8 * per), NOALLOC_SCRATCH_BYTES);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    for (int64_t e0 = 0; e0 < E; e0 += chunk) {
+        const int64_t c = std::min(chunk, E - e0);
+        ElemDesc *desc = reinterpret_cast<ElemDesc *>(ctx->scratch);
+        // regions start on 256-byte boundaries (32 doubles)
+        double *alpha = ctx->scratch + (c * desc_d + 31) / 32 * 32;
+        double *mom = alpha + (c * na + 31) / 32 * 32;
+        hipLaunchKernelGGL(k_uniform_desc, dim3((unsigned)((c + 255) / 256)), dim3(256), 0, st, desc, c, N, Qu, Qv,
+                           Qw, ndof2, na, nm);
+        launch_coupling(problem, desc, 0, c, nodes ? nodes + e0 * 81 : nullptr, material + e0 * mstride, kind,
+                        stride, ctx->d_tab, alpha, status + e0, nullptr, st);
+        launch_moments(problem, ms, desc, 0, c, alpha, ctx->d_tab, mom, nullptr, nullptr, st);
+        if (launch_contract(problem, N, desc, nullptr, 0, c, ctx->d_tab, mom, out + e0 * ndof2, status + e0,
+                            terms->stiff_scale, terms->mass_scale, st) != 0)
+            return fail(ctx, P2S_EINVAL, "noalloc: no contraction kernel for problem %d order %d", problem, N);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    return P2S_OK;
 }
 
 int p2s_plan_set_schedule(p2s_plan plan, int mode, int wgs_per_cu)
