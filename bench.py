@@ -307,6 +307,77 @@ def compact_configs(torch, p2s, ctx, W, oracle, steps, warmup, log):
     return res
 
 
+TABLE1_ORDERS = (3, 4, 6, 8, 10, 12, 14, 16, 18)
+# the paper's Table I: fill times (s) of the product-to-sum and the direct
+# method for its 16-element mesh, per order M = N (Core2Duo 2.5 GHz; context)
+PAPER_TABLE1 = {3: (0.104, 0.100), 4: (0.121, 0.148), 6: (0.170, 0.428), 8: (0.229, 1.103),
+                10: (0.328, 2.375), 12: (0.461, 4.65), 14: (0.634, 8.21), 16: (0.934, 14.0), 18: (1.29, 22.14)}
+
+
+def cheb2d_table1(torch, p2s, ctx, W, log, copies=256, reps=5):
+    """The paper's 2-D example (Section III, Table I) on its stand-in mesh:
+    per order M = N, the fill of the 16 elements by the product-to-sum form
+    and by direct quadrature on the GPU (one call each, the paper's batch),
+    the same 16 elements repeated `copies` times (throughput), the largest
+    difference between the two forms and against the oracle, and the
+    measured and predicted (D/15, D = MN, Section IV) reduction factors."""
+    from oracle import cheb2d as ocheb
+    rows = []
+    mesh = W.cheb2d_mesh()
+    big = W.cheb2d_replicated(copies)
+    dev = torch.device("cuda", 0)
+    for M in TABLE1_ORDERS:
+        Q = min(32, M + 6)
+        row = {"M": M, "Q": Q, "dofs": 2 * M * (M + 1)}
+        for name, w in (("mesh16", mesh), ("replicated", big)):
+            c = ctx.cheb2d(w.E, M, Q)
+            nodes = torch.from_numpy(w.nodes).to(dev)
+            mat = torch.from_numpy(w.mat).to(dev)
+            out = torch.empty(w.E * c.ndof * c.ndof, dtype=torch.float64, device=dev)
+            st = torch.empty(w.E, dtype=torch.int32, device=dev)
+            res = {}
+            for meth, key in ((p2s.METHOD_P2S, "p2s"), (p2s.METHOD_DIRECT, "direct")):
+                c.execute(nodes, mat, meth, out=out, status=st)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    c.execute(nodes, mat, meth, out=out, status=st)
+                torch.cuda.synchronize()
+                res[key + "_ms"] = (time.perf_counter() - t0) * 1e3 / reps
+                if name == "mesh16":
+                    res[key + "_out"] = out.view(w.E, -1).cpu().numpy().copy()
+            if name == "mesh16":
+                ref, _ = ocheb.fill(w.nodes, w.mat, M, Q)
+                nrm = np.linalg.norm(ref, axis=1)
+                row["max_rel_err_p2s_vs_oracle"] = float((np.linalg.norm(res["p2s_out"] - ref, axis=1) / nrm).max())
+                row["max_rel_err_direct_vs_oracle"] = float(
+                    (np.linalg.norm(res["direct_out"] - ref, axis=1) / nrm).max())
+                row["mesh16_p2s_ms"] = round(res["p2s_ms"], 4)
+                row["mesh16_direct_ms"] = round(res["direct_ms"], 4)
+            else:
+                c.profile(True)
+                c.execute(nodes, mat, p2s.METHOD_P2S, out=out, status=st)
+                ms = c.profile(False)
+                nd = c.ndof
+                gbs = w.E * (8 * nd * nd + 8 * 4 * (2 * M + 1) ** 2) / (ms[2] * 1e-3) / 1e9
+                row["replicated_elements"] = w.E
+                row["replicated_p2s_elements_per_s"] = round(w.E / (res["p2s_ms"] * 1e-3), 1)
+                row["replicated_direct_elements_per_s"] = round(w.E / (res["direct_ms"] * 1e-3), 1)
+                row["p2s_gather_roofline_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+            del out, c
+        row["measured_reduction_mesh16"] = round(row["mesh16_direct_ms"] / row["mesh16_p2s_ms"], 3)
+        row["measured_reduction_replicated"] = round(row["replicated_p2s_elements_per_s"] /
+                                                     row["replicated_direct_elements_per_s"], 3)
+        row["predicted_reduction_D_over_15"] = round(M * M / 15.0, 3)
+        row["paper_reduction"] = round(PAPER_TABLE1[M][1] / PAPER_TABLE1[M][0], 3)
+        rows.append(row)
+        log("cheb2d M=%d done" % M)
+    torch.cuda.empty_cache()
+    return {"description": "paper's 2-D example (curl-curl + mass, Chebyshev basis of eq. (6), eps_r = "
+                           "2 exp(x+y+2)) on a 16-element stand-in mesh of the Fig. 1 domain; Q = min(32, M+6)",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -528,6 +599,7 @@ def main():
         plan = None
         torch.cuda.empty_cache()
         result["configs"] = compact_configs(torch, p2s, ctx, W, oracle, args.steps, args.warmup, log)
+        result["configs"]["cheb2d_table1"] = cheb2d_table1(torch, p2s, ctx, W, log)
     print(json.dumps(result), flush=True)
 
 

@@ -314,6 +314,40 @@ int p2s_fill_uniform_noalloc(p2s_ctx ctx, const p2s_terms *terms, int64_t E, int
                              int Qu, int Qv, int Qw, const double *nodes, const double *material,
                              double *out, uint32_t *status, void *stream);
 
+/* ------------------------------------------------------------------------
+ * The paper's own instance (Section III): 2-D curl-curl + mass element
+ * matrices (eqs. (5), (7)) of curved quadrilaterals with the Chebyshev vector
+ * basis of eq. (6), M = N:
+ *   u-functions U_m(u) T_n(v), m < M, n <= M   (dof m (M+1) + n),
+ *   v-functions T_m(u) U_n(v), m <= M, n < M   (dof M (M+1) + m M + n),
+ * covariant components; entries of eqs. (8)-(15) with mu_r = 1, as
+ * stiff_scale * S + mass_scale * M.  Geometry: fourth-order quadrilateral,
+ * nodes [device][E][25][2], node (i,j) at i + 5 j on the reference points
+ * (-1 + i/2, -1 + j/2).  Material [device][E][4]: eps_r = p0 exp(p1 x + p2 y
+ * + p3) (the paper's 2 exp(x + y + 2) is (2, 1, 1, 2)).  Q x Q Gauss points.
+ * method P2S_METHOD_P2S: the product-to-sum method of eqs. (16)-(19) (four
+ * starting-point integral tables per element, every entry a gather-add of at
+ * most eight of them); P2S_METHOD_DIRECT: direct 2-D quadrature of every
+ * entry (the comparison of Table I).  out [device] E dense row-major blocks
+ * of p2s_cheb2d_num_dofs(M)^2 doubles; status [device][E] (P2S_STATUS_DETJ,
+ * and P2S_STATUS_NONFINITE for the product-to-sum form).
+ * create: M in 1..18 (P2S_EORDER), Q in 1..P2S_MAX_Q (P2S_EQUAD); allocates
+ * the workspace of E elements.  execute: enqueues on `stream`, allocates
+ * nothing.  profile(enable, ms): ms [host][3] (may be NULL) receives the
+ * mean milliseconds per execution of the geometry, moment (or nothing) and
+ * contraction (or direct) kernels since the last call; while enabled,
+ * execute waits for its own kernels. */
+typedef struct p2s_cheb2d_s *p2s_cheb2d;
+int64_t p2s_cheb2d_num_dofs(int M);
+int p2s_cheb2d_create(p2s_ctx ctx, int64_t E, int M, int Q, p2s_cheb2d *out);
+int p2s_cheb2d_execute(p2s_cheb2d plan, int method, const double *nodes, const double *material,
+                       double stiff_scale, double mass_scale, double *out, uint32_t *status,
+                       void *stream);
+int p2s_cheb2d_profile(p2s_cheb2d plan, int enable, double *ms);
+void p2s_cheb2d_destroy(p2s_cheb2d plan);
+/* Device of a context (-1 for NULL). */
+int p2s_context_device(p2s_ctx ctx);
+
 /* Stage outputs, for verification of each step against its definition.
  * Coupling samples: alpha [device][E][F][Qu*Qv*Qw] (unweighted, packed
  * field order of P2S_ALPHA_SAMPLED).  Moments: [device][E][F][K][K][K],

@@ -37,7 +37,8 @@ EXPORTS = (
     "p2s_plan_replay", "p2s_mlp_init", "p2s_mlp_set_params", "p2s_mlp_get_params", "p2s_mlp_save",
     "p2s_mlp_load", "p2s_features", "p2s_mlp_forward", "p2s_mlp_gradients", "p2s_mlp_train_step",
     "p2s_mlp_predict", "p2s_plan_set_learned", "p2s_plan_rules", "p2s_rel_error", "p2s_plan_tail_values",
-    "p2s_plan_tail_records", "p2s_fill_uniform_noalloc",
+    "p2s_plan_tail_records", "p2s_fill_uniform_noalloc", "p2s_cheb2d_num_dofs", "p2s_cheb2d_create",
+    "p2s_cheb2d_execute", "p2s_cheb2d_profile", "p2s_cheb2d_destroy", "p2s_context_device",
 )
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 85, 128, 57, 34873
 KMIN, KMAX = 6, 24
@@ -81,6 +82,14 @@ def load():
         lib.p2s_fill_element_matrices.argtypes = [vp, ctypes.POINTER(_Terms), i64, vp, vp, vp, vp, vp, vp, vp]
         lib.p2s_fill_uniform_noalloc.argtypes = [vp, ctypes.POINTER(_Terms), i64, i32, i32, i32, i32, vp, vp, vp,
                                                  vp, vp]
+        lib.p2s_cheb2d_num_dofs.argtypes = [i32]
+        lib.p2s_cheb2d_num_dofs.restype = i64
+        lib.p2s_cheb2d_create.argtypes = [vp, i64, i32, i32, ctypes.POINTER(vp)]
+        lib.p2s_cheb2d_execute.argtypes = [vp, i32, vp, vp, d, d, vp, vp, vp]
+        lib.p2s_cheb2d_profile.argtypes = [vp, i32, vp]
+        lib.p2s_cheb2d_destroy.argtypes = [vp]
+        lib.p2s_cheb2d_destroy.restype = None
+        lib.p2s_context_device.argtypes = [vp]
         lib.p2s_plan_coupling.argtypes = [vp, vp, vp, vp, vp]
         lib.p2s_plan_moments.argtypes = [vp, vp, vp, vp, vp]
         lib.p2s_plan_profile.argtypes = [vp, i32]
@@ -115,7 +124,8 @@ def load():
                   "p2s_mlp_save", "p2s_mlp_load", "p2s_features", "p2s_mlp_forward", "p2s_mlp_gradients",
                   "p2s_mlp_train_step", "p2s_mlp_predict", "p2s_plan_set_learned", "p2s_plan_rules",
                   "p2s_rel_error", "p2s_plan_tail_values", "p2s_plan_tail_records",
-                  "p2s_fill_uniform_noalloc"):
+                  "p2s_fill_uniform_noalloc", "p2s_cheb2d_create", "p2s_cheb2d_execute", "p2s_cheb2d_profile",
+                  "p2s_context_device"):
             getattr(lib, f).restype = i32
         _lib = lib
     return _lib
@@ -297,6 +307,9 @@ class Context:
                                              _dev_ptr(status), _stream(stream))
         self.check(rc, "p2s_fill_uniform_noalloc")
 
+    def cheb2d(self, E, M, Q) -> "Cheb2D":
+        return Cheb2D(self, E, M, Q)
+
     def plan(self, problem, material, orders, quad, precision=FP64, method=METHOD_P2S,
              stiff_scale=1.0, mass_scale=1.0) -> "Plan":
         return Plan(self, terms(problem, material, precision, method, stiff_scale, mass_scale), orders, quad)
@@ -419,6 +432,53 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             load().p2s_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Cheb2D:
+    """The paper's 2-D Chebyshev example (p2s_cheb2d_*): workspace for E
+    elements of order M = N with Q x Q Gauss points."""
+
+    def __init__(self, ctx: Context, E: int, M: int, Q: int):
+        self.ctx, self.E, self.M, self.Q = ctx, int(E), int(M), int(Q)
+        h = ctypes.c_void_p()
+        rc = load().p2s_cheb2d_create(ctx._h, self.E, self.M, self.Q, ctypes.byref(h))
+        if rc != 0:
+            raise P2SError("p2s_cheb2d_create failed (%d)" % rc)
+        self._h = h
+        self.ndof = int(load().p2s_cheb2d_num_dofs(self.M))
+
+    def execute(self, nodes, material, method=METHOD_P2S, stiff_scale=1.0, mass_scale=1.0, out=None,
+                status=None, stream=None):
+        import torch
+        dev = torch.device("cuda", self.ctx.device)
+        if out is None:
+            out = torch.empty(self.E * self.ndof * self.ndof, dtype=torch.float64, device=dev)
+        if status is None:
+            status = torch.empty(self.E, dtype=torch.int32, device=dev)
+        rc = load().p2s_cheb2d_execute(self._h, int(method), _dev_ptr(nodes), _dev_ptr(material),
+                                       float(stiff_scale), float(mass_scale), _dev_ptr(out), _dev_ptr(status),
+                                       _stream(stream))
+        if rc != 0:
+            raise P2SError("p2s_cheb2d_execute failed (%d)" % rc)
+        return out, status
+
+    def profile(self, enable=True):
+        """Mean ms per execution of (geometry, moments, contraction or
+        direct) since the last call; then enable or disable timing."""
+        ms = np.zeros(3)
+        load().p2s_cheb2d_profile(self._h, int(enable), _np_ptr(ms))
+        return ms
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().p2s_cheb2d_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -172,6 +172,8 @@ extern "C" {
 
 const char *p2s_last_error(p2s_ctx ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
+int p2s_context_device(p2s_ctx ctx) { return ctx ? ctx->device : -1; }
+
 int64_t p2s_num_dofs(int problem, int N)
 {
     if ((problem != P2S_SCALAR && problem != P2S_VECTOR) || N < 2 || N > P2S_MAX_ORDER) return -1;

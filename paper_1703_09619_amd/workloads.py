@@ -195,7 +195,8 @@ def subset(w: Workload, idx) -> Workload:
     idx = np.asarray(idx)
     out = Workload(w)
     for k in ("nodes", "mat", "orders", "quad", "amp", "shrink_steps"):
-        out[k] = np.ascontiguousarray(w[k][idx])
+        if k in w:
+            out[k] = np.ascontiguousarray(w[k][idx])
     out["E"] = len(idx)
     return out
 
@@ -203,3 +204,46 @@ def subset(w: Workload, idx) -> Workload:
 def num_dofs(problem: int, N: int) -> int:
     """Degrees of freedom of one element (sizes the output, not arithmetic)."""
     return N ** 3 if problem == SCALAR else 3 * (N - 1) * N * N
+
+
+# ---------------------------------------------------------------------------
+# The paper's 2-D example (Section III): a stand-in for the mesh of its
+# Fig. 2, whose node coordinates the paper does not give.  The domain is the
+# curved quadrilateral bounded by y = -f(x), y = f(x), x = -g(y), x = g(y) with
+# the caption's f(x) = -0.2 (x^2 - 1)^2 + 1 and g(y) = 0.2 (y^2 - 1)^2 + 1
+# (corners at (+-1, +-1)).  Transfinite (Coons) interpolation of its four
+# edges maps the reference square onto it as (s, t) -> (s g(t), t f(s)),
+# which is of degree 4 in each variable, so fourth-order quadrilaterals
+# represent it exactly.  The square is split into nx x ny elements.
+
+CHEB2D_MATERIAL = (2.0, 1.0, 1.0, 2.0)  # eps_r = 2 exp(x + y + 2)
+
+
+def cheb2d_mesh(nx: int = 4, ny: int = 4) -> Workload:
+    """nodes [nx*ny][25][2] (node (i,j) at i + 5 j on the reference points
+    (-1 + i/2, -1 + j/2)) and material [nx*ny][4] of the stand-in mesh."""
+    f = lambda x: -0.2 * (x * x - 1.0) ** 2 + 1.0
+    g = lambda y: 0.2 * (y * y - 1.0) ** 2 + 1.0
+    ref = np.array([-1.0, -0.5, 0.0, 0.5, 1.0])
+    E = nx * ny
+    nodes = np.zeros((E, 25, 2))
+    for iy in range(ny):
+        for ix in range(nx):
+            e = iy * nx + ix
+            s0, s1 = -1.0 + 2.0 * ix / nx, -1.0 + 2.0 * (ix + 1) / nx
+            t0, t1 = -1.0 + 2.0 * iy / ny, -1.0 + 2.0 * (iy + 1) / ny
+            for j in range(5):
+                for i in range(5):
+                    s = s0 + 0.5 * (ref[i] + 1.0) * (s1 - s0)
+                    t = t0 + 0.5 * (ref[j] + 1.0) * (t1 - t0)
+                    nodes[e, i + 5 * j] = (s * g(t), t * f(s))
+    mat = np.tile(np.array(CHEB2D_MATERIAL), (E, 1))
+    return Workload(name="cheb2d_mesh", E=E, nodes=nodes, mat=mat)
+
+
+def cheb2d_replicated(copies: int) -> Workload:
+    """The 16-element stand-in mesh repeated `copies` times (a larger batch
+    of the same elements, for throughput)."""
+    m = cheb2d_mesh()
+    return Workload(name="cheb2d_replicated", E=m.E * copies, nodes=np.tile(m.nodes, (copies, 1, 1)),
+                    mat=np.tile(m.mat, (copies, 1)))

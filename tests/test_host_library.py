@@ -26,7 +26,7 @@ def p2s():
 def header_functions():
     src = open(os.path.join(ROOT, "include", "p2s.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(p2s_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(p2s_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol(p2s):
