@@ -478,7 +478,7 @@ def main():
         "metric": METRIC, "value": round(value, 1), "unit": "element matrices/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 (hi/lo split operands) + f64" if split else "f64",
+        "dtype": "f32 MFMA on exact 10-bit operand slices + f64" if split else "f64",
         "data": "synthetic (seeded curved triquadratic hexahedra and analytic materials)",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "elements": w.E,
                    "orders": sorted(set(int(n) for n in w.orders)), "gauss_points": w.quad[0].tolist(),

@@ -89,9 +89,13 @@ typedef enum {
 } p2s_material;
 
 /* Arithmetic of stages (a) and (c).  FP64 throughout, or the split-FP32
- * form: moments and contraction on FP32 matrix cores with each operand
- * split into two FP32 parts, map/Jacobian/coupling/tables/final
- * accumulation in FP64. */
+ * form: every product of the moment and contraction GEMMs runs on the FP32
+ * matrix cores on exact operand slices (per 16x16x4 step, each row and
+ * column scaled by a power of two and split into four 10-bit integer
+ * slices; the slice products of each order are summed exactly in FP32 and
+ * added into FP64), with map/Jacobian/coupling/tables, intermediates and
+ * every sum in FP64.  Relative error about 1e-11.  Uniform plans with at
+ * most 16 Gauss points per axis (P2S_EQUAD otherwise). */
 typedef enum { P2S_FP64 = 0, P2S_SPLIT_FP32 = 1 } p2s_precision;
 
 /* Method: product-to-sum (the paper's method, Section II eqs. (3)-(4)),

@@ -26,7 +26,6 @@ using namespace p2s;
 struct p2s_ctx_s {
     int device = 0;
     double *d_tab = nullptr;
-    float *d_tab32 = nullptr;  // hi/lo FP32 split tables of the split-precision path
     std::string err;
     // learned quadrature order: network parameters, Adam state, training scratch
     bool mlp_ready = false;
@@ -234,12 +233,6 @@ int p2s_create(p2s_ctx *out, int device)
         p2s_destroy(ctx);
         return fail(nullptr, P2S_ENOMEM, "p2s_create: table allocation failed");
     }
-    std::vector<float> tab32(T32_SIZE);
-    build_split_tables(tab.data(), tab32.data());
-    if (hipMalloc(&ctx->d_tab32, sizeof(float) * T32_SIZE) != hipSuccess) {
-        p2s_destroy(ctx);
-        return fail(nullptr, P2S_ENOMEM, "p2s_create: table allocation failed");
-    }
     {
         // with the context's device current: this GPU's copy of the scratch
         void *p = nullptr;
@@ -251,8 +244,7 @@ int p2s_create(p2s_ctx *out, int device)
         ctx->scratch = static_cast<double *>(p);
     }
     if (hipMemcpy(ctx->d_tab, tab.data(), sizeof(double) * TAB_SIZE, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(ctx->d_tab32, tab32.data(), sizeof(float) * T32_SIZE, hipMemcpyHostToDevice) != hipSuccess ||
-        prepare_kernels() != 0) {
+        prepare_kernels() != 0 || prepare_split_kernels() != 0) {
         p2s_destroy(ctx);
         return fail(nullptr, P2S_EHIP, "p2s_create: table upload failed");
     }
@@ -267,7 +259,6 @@ void p2s_destroy(p2s_ctx ctx)
     for (p2s_plan p : ctx->fill_cache) p2s_plan_destroy(p);
     ctx->fill_cache.clear();
     if (ctx->d_tab) hipFree(ctx->d_tab);
-    if (ctx->d_tab32) hipFree(ctx->d_tab32);
     for (float *p : {ctx->d_mlp, ctx->d_grad, ctx->d_adam_m, ctx->d_adam_v, ctx->d_h1, ctx->d_h2, ctx->d_z,
                      ctx->d_dz, ctx->d_dh2, ctx->d_dh1, ctx->d_lossb})
         if (p) hipFree(p);
@@ -586,8 +577,7 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         const bool split = plan->terms.precision == P2S_SPLIT_FP32;
         prof_begin(plan, 1, st);
         if (split && stop != STOP_TAILREC)
-            launch_moments_split(problem, plan->d_desc, c.e0, c.count, plan->d_alpha, ctx->d_tab32,
-                                 reinterpret_cast<float *>(plan->d_mom), st);
+            launch_moments_split(problem, plan->d_desc, c.e0, c.count, plan->d_alpha, ctx->d_tab, plan->d_mom, st);
         else if (!plan->uniform && !learned && stop != STOP_TAILREC)
             // mixed orders: one launch per order class, each with the LDS
             // shape of its own elements rather than of the largest order
@@ -614,17 +604,13 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         if (stop == STOP_MOMENTS) {
             const int K = 2 * plan->N - 1;
             const int64_t per = (int64_t)F * K * K * K;
-            if (split)
-                launch_widen(per * c.count, reinterpret_cast<const float *>(plan->d_mom), stage_out + c.e0 * per, st);
-            else
-                HIP_TRY(ctx, hipMemcpyAsync(stage_out + c.e0 * per, plan->d_mom, sizeof(double) * per * c.count,
-                                            hipMemcpyDeviceToDevice, st));
+            HIP_TRY(ctx, hipMemcpyAsync(stage_out + c.e0 * per, plan->d_mom, sizeof(double) * per * c.count,
+                                        hipMemcpyDeviceToDevice, st));
             continue;
         }
         prof_begin(plan, 2, st);
         if (split) {
-            launch_contract_split(problem, plan->N, plan->d_desc, c.e0, c.count, ctx->d_tab32,
-                                  reinterpret_cast<const float *>(plan->d_mom), out, status,
+            launch_contract_split(problem, plan->N, plan->d_desc, c.e0, c.count, ctx->d_tab, plan->d_mom, out, status,
                                   plan->terms.stiff_scale, plan->terms.mass_scale, st);
         } else if (plan->mode == 1) {
             launch_contract_persistent(problem, plan->d_desc, plan->d_items + c.item0, c.nitem, plan->d_counter,

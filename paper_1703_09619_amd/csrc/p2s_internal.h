@@ -121,18 +121,6 @@ constexpr int TAIL_REC = 16;
 // in one 16-row matrix-core tile: orders up to 6
 constexpr int TAIL_MAXN = 6;
 
-// FP32 two-term split tables of the split-precision path (floats):
-// x = hi + lo with hi = fl32(x), lo = fl32(x - hi), for the linearization
-// coefficients lin[t][m1][m2][k] (k < KPAD) and the moment weights
-// legw[Q][k][a] (k, a < 16).
-constexpr int T32_LIN = NTYPE * MAXN * MAXN * KPAD;
-constexpr int T32_LEGW_Q = 16 * 16;
-constexpr int T32_LEGW = (MAXQ + 1) * T32_LEGW_Q;
-constexpr int T32_LIN_H = 0;
-constexpr int T32_LIN_L = T32_LIN_H + T32_LIN;
-constexpr int T32_LEGW_H = T32_LIN_L + T32_LIN;
-constexpr int T32_LEGW_L = T32_LEGW_H + T32_LEGW;
-constexpr int T32_SIZE = T32_LEGW_L + T32_LEGW;
 // the split path samples at most this many points per axis (one MFMA
 // K-block of 16)
 constexpr int SPLIT_MAXQ = 16;

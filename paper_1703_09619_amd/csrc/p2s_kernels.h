@@ -48,13 +48,13 @@ int launch_contract_persistent(int problem, const ElemDesc *desc, const WorkItem
                                uint32_t *status, double sK, double sM, hipStream_t st);
 
 // Split-FP32 form of the moment stage and the contraction (p2s_split.hip):
-// moments written as FP32 at mom32 + mom_off; uniform plans, Q <= 16.
+// FP32 matrix-core products on exact operand slices, FP64 sums; FP64
+// moments at mom + mom_off; uniform plans, Q <= 16.
 void launch_moments_split(int problem, const ElemDesc *desc, int64_t e0, int64_t count, const double *alpha,
-                          const float *t32, float *mom32, hipStream_t st);
-void launch_contract_split(int problem, int N, const ElemDesc *desc, int64_t e0, int64_t count, const float *t32,
-                           const float *mom32, double *out, uint32_t *status, double sK, double sM, hipStream_t st);
-// dst[i] = (double)src[i]
-void launch_widen(int64_t n, const float *src, double *dst, hipStream_t st);
+                          const double *tab, double *mom, hipStream_t st);
+void launch_contract_split(int problem, int N, const ElemDesc *desc, int64_t e0, int64_t count, const double *tab,
+                           const double *mom, double *out, uint32_t *status, double sK, double sM, hipStream_t st);
+int prepare_split_kernels();
 
 // Direct quadrature of eq. (2) (baseline method), from coupling samples.
 void launch_direct(int problem, int N, const ElemDesc *desc, int64_t e0, int64_t count, const double *tab,

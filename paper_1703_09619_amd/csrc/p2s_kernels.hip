@@ -412,8 +412,14 @@ __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const d
     }
 }
 
+// With tail records the LDS holds the carried tail rows (about 114 KB at 24
+// points per axis, one workgroup per CU), so that form runs eight waves per
+// workgroup instead of four.
+constexpr int MOMENTS_TAIL_THREADS = 512;
+
 template <bool TAIL>
-__global__ __launch_bounds__(256) void k_moments(const ElemDesc *__restrict__ desc, int64_t e0, int F,
+__global__ __launch_bounds__(TAIL ? MOMENTS_TAIL_THREADS : 256) void k_moments(const ElemDesc *__restrict__ desc,
+                                                                             int64_t e0, int F,
                                                  const double *__restrict__ alpha,
                                                  const double *__restrict__ tab,
                                                  double *__restrict__ mom, int p2off,
@@ -546,8 +552,9 @@ __global__ __launch_bounds__(256) void k_moments_valu(const ElemDesc *__restrict
 
 // LDS layout of k_moments for the largest order and rule of a plan:
 // P1 [K][Qv*Qw] followed by P2 [K][K][Qw | 1]; the staged K^3 tile of
-// pass 3 reuses P1 when it fits there, else follows P2; at least 4 waves x
-// TAIL_REC doubles (the tail-record reduction reuses the start).
+// pass 3 reuses P1 when it fits there, else follows P2; at least one
+// TAIL_REC per wave of the tail form (the tail-record reduction reuses the
+// start).
 // With tail records P1 and P2 carry four more rows per reduced axis: P1
 // [K+4][Qv*Qw], P2 [K+4][K+4][Qw | 1].
 int moments_p2_offset(int maxN, int maxQvw, bool tail) { return maxQvw * (2 * maxN - 1 + (tail ? 4 : 0)); }
@@ -557,7 +564,9 @@ size_t moments_smem_bytes(int maxN, int maxQw, int maxQvw, bool tail)
     const size_t p2 = (size_t)moments_p2_offset(maxN, maxQvw, tail);
     size_t n = p2 + (size_t)(K4 * K4 * (maxQw | 1));
     if ((size_t)(K * K * K) > p2) n += (size_t)(K * K * K);
-    return sizeof(double) * (n > 4 * TAIL_REC ? n : 4 * TAIL_REC);
+    // the tail-record reduction reuses the start: one record per wave
+    const size_t red = (size_t)(MOMENTS_TAIL_THREADS / 64) * TAIL_REC;
+    return sizeof(double) * (n > red ? n : red);
 }
 // LDS layout of k_moments_valu: P1 [Qu*Qv][K+1] followed by P2 [Qu][K][K+1],
 // which first holds the staged samples [Qu*Qv][Qw|1].
@@ -627,7 +636,7 @@ void launch_moments(int problem, const MomentShape &m, const ElemDesc *desc, int
     if (count <= 0) return;
     const int F = num_fields(problem);
     if (tailst)
-        hipLaunchKernelGGL(k_moments<true>, dim3((unsigned)count, F), dim3(256),
+        hipLaunchKernelGGL(k_moments<true>, dim3((unsigned)count, F), dim3(MOMENTS_TAIL_THREADS),
                            moments_smem_bytes(m.maxN, m.maxQw, m.maxQvw, true), st, desc, e0, F, alpha, tab, mom,
                            moments_p2_offset(m.maxN, m.maxQvw, true), only, tailst, elist);
     else if (m.maxQ <= SPLIT_MAXQ)

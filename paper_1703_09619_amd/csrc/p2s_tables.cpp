@@ -110,22 +110,6 @@ int linearization(int xf, int m1, int yf, int m2, double *coef)
     return 0;
 }
 
-void build_split_tables(const double *tab, float *t32)
-{
-    auto split = [](double x, float &hi, float &lo) {
-        hi = (float)x;
-        lo = (float)(x - (double)hi);
-    };
-    for (int i = 0; i < T32_LIN; ++i) split(tab[TAB_LIN + i], t32[T32_LIN_H + i], t32[T32_LIN_L + i]);
-    for (int Q = 0; Q <= MAXQ; ++Q)
-        for (int k = 0; k < 16; ++k)
-            for (int a = 0; a < 16; ++a) {
-                const double x = a < MAXQ ? tab[TAB_LEGW + Q * LEGW_STRIDE_Q + k * MAXQ + a] : 0.0;
-                const int o = Q * T32_LEGW_Q + k * 16 + a;
-                split(x, t32[T32_LEGW_H + o], t32[T32_LEGW_L + o]);
-            }
-}
-
 void build_tables(double *tab)
 {
     std::memset(tab, 0, sizeof(double) * TAB_SIZE);

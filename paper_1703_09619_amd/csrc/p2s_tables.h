@@ -11,8 +11,5 @@ int gauss_rule(int Q, double *x, double *w);
 int linearization(int xf, int m1, int yf, int m2, double *coef);
 // Fill the whole table buffer (TAB_SIZE doubles, layout in p2s_internal.h).
 void build_tables(double *tab);
-// FP32 hi/lo split copies of the linearization and moment-weight tables
-// (T32_SIZE floats) from a built table buffer.
-void build_split_tables(const double *tab, float *t32);
 
 }  // namespace p2s
