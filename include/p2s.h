@@ -108,6 +108,13 @@ typedef enum { P2S_FP64 = 0, P2S_SPLIT_FP32 = 1 } p2s_precision;
  *             (P2S_EQUAD otherwise); FP64. */
 typedef enum { P2S_METHOD_P2S = 0, P2S_METHOD_DIRECT = 1, P2S_METHOD_DIRECT_SF = 2 } p2s_method;
 
+/* Output layout of each element's (symmetric) matrix: the dense row-major
+ * block, or its upper triangle packed row by row (row r holds columns
+ * c >= r: entry (r, c) at r*n - r*(r-1)/2 + (c - r), n = dofs), which
+ * halves the bytes written.  The packed layout is available for the FP64
+ * product-to-sum method with per-order-class launches (schedule mode 0). */
+typedef enum { P2S_OUTPUT_DENSE = 0, P2S_OUTPUT_PACKED_UPPER = 1 } p2s_output;
+
 typedef struct {
     int32_t problem;     /* p2s_problem                      */
     int32_t material;    /* p2s_material                     */
@@ -115,6 +122,8 @@ typedef struct {
     int32_t method;      /* p2s_method                       */
     double stiff_scale;  /* weight of the stiffness term (1) */
     double mass_scale;   /* weight of the mass term (1)      */
+    int32_t output;      /* p2s_output (dense)               */
+    int32_t reserved;    /* 0                                */
 } p2s_terms;
 
 #define P2S_MAX_ORDER 8
@@ -143,6 +152,9 @@ int64_t p2s_num_dofs(int problem, int N);
  * row-major block, offsets[E] the total.  orders [host][E],
  * offsets [host][E+1]. */
 int p2s_layout(int problem, int64_t E, const int32_t *orders, int64_t *offsets);
+/* The same for an output layout (p2s_output): packed blocks hold
+ * n (n + 1) / 2 doubles. */
+int p2s_layout_output(int problem, int output, int64_t E, const int32_t *orders, int64_t *offsets);
 
 /* Plan: the schedule, per-element descriptors and workspace for one batch
  * shape (E, orders [host][E], quad [host][E][3] Gauss points per axis).

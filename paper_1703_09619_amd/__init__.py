@@ -23,13 +23,14 @@ SCALAR, VECTOR = 0, 1
 MAT_SINCOSEXP, MAT_ROTDIAG, MAT_PLANEWAVE, ALPHA_SAMPLED = 0, 1, 2, 3
 FP64, SPLIT_FP32 = 0, 1
 METHOD_P2S, METHOD_DIRECT, METHOD_DIRECT_SF = 0, 1, 2
+OUTPUT_DENSE, OUTPUT_PACKED_UPPER = 0, 1
 FAM_PHI, FAM_DPHI, FAM_PSI = 0, 1, 2
 STATUS_DETJ, STATUS_NONFINITE, STATUS_FALLBACK = 1, 2, 4
 MAX_ORDER, MAX_Q = 8, 32
 
 # every symbol the C ABI exports (include/p2s.h)
 EXPORTS = (
-    "p2s_create", "p2s_destroy", "p2s_last_error", "p2s_num_dofs", "p2s_layout",
+    "p2s_create", "p2s_destroy", "p2s_last_error", "p2s_num_dofs", "p2s_layout", "p2s_layout_output",
     "p2s_plan_create", "p2s_plan_execute", "p2s_plan_workspace_bytes", "p2s_plan_destroy",
     "p2s_fill_element_matrices", "p2s_plan_coupling", "p2s_plan_moments",
     "p2s_gauss_rule", "p2s_linearization", "p2s_plan_profile", "p2s_plan_profile_read",
@@ -51,7 +52,8 @@ class P2SError(RuntimeError):
 class _Terms(ctypes.Structure):
     _fields_ = [("problem", ctypes.c_int32), ("material", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("stiff_scale", ctypes.c_double), ("mass_scale", ctypes.c_double)]
+                ("stiff_scale", ctypes.c_double), ("mass_scale", ctypes.c_double),
+                ("output", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -73,6 +75,7 @@ def load():
         lib.p2s_num_dofs.argtypes = [i32, i32]
         lib.p2s_num_dofs.restype = i64
         lib.p2s_layout.argtypes = [i32, i64, vp, vp]
+        lib.p2s_layout_output.argtypes = [i32, i32, i64, vp, vp]
         lib.p2s_plan_create.argtypes = [vp, ctypes.POINTER(_Terms), i64, vp, vp, ctypes.POINTER(vp)]
         lib.p2s_plan_execute.argtypes = [vp, vp, vp, vp, vp, vp]
         lib.p2s_plan_workspace_bytes.argtypes = [vp]
@@ -116,7 +119,7 @@ def load():
         lib.p2s_rel_error.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
         lib.p2s_gauss_rule.argtypes = [i32, vp, vp]
         lib.p2s_linearization.argtypes = [i32, i32, i32, i32, vp]
-        for f in ("p2s_create", "p2s_layout", "p2s_plan_create", "p2s_plan_execute",
+        for f in ("p2s_create", "p2s_layout", "p2s_layout_output", "p2s_plan_create", "p2s_plan_execute",
                   "p2s_fill_element_matrices", "p2s_plan_coupling", "p2s_plan_moments",
                   "p2s_gauss_rule", "p2s_linearization", "p2s_plan_profile", "p2s_plan_profile_read",
                   "p2s_plan_set_schedule", "p2s_plan_get_schedule", "p2s_plan_autotune", "p2s_plan_capture",
@@ -149,10 +152,10 @@ def num_dofs(problem: int, N: int) -> int:
     return int(load().p2s_num_dofs(problem, N))
 
 
-def layout(problem: int, orders) -> np.ndarray:
+def layout(problem: int, orders, output: int = OUTPUT_DENSE) -> np.ndarray:
     orders = np.ascontiguousarray(orders, dtype=np.int32)
     off = np.zeros(len(orders) + 1, dtype=np.int64)
-    rc = load().p2s_layout(problem, len(orders), _np_ptr(orders), _np_ptr(off))
+    rc = load().p2s_layout_output(problem, output, len(orders), _np_ptr(orders), _np_ptr(off))
     if rc != 0:
         raise P2SError("p2s_layout failed: %d" % rc)
     return off
@@ -176,8 +179,8 @@ def linearization(xfam: int, m1: int, yfam: int, m2: int) -> np.ndarray:
 
 
 def terms(problem: int, material: int, precision: int = FP64, method: int = METHOD_P2S,
-          stiff_scale: float = 1.0, mass_scale: float = 1.0) -> _Terms:
-    return _Terms(problem, material, precision, method, stiff_scale, mass_scale)
+          stiff_scale: float = 1.0, mass_scale: float = 1.0, output: int = OUTPUT_DENSE) -> _Terms:
+    return _Terms(problem, material, precision, method, stiff_scale, mass_scale, output, 0)
 
 
 class Context:
@@ -311,8 +314,9 @@ class Context:
         return Cheb2D(self, E, M, Q)
 
     def plan(self, problem, material, orders, quad, precision=FP64, method=METHOD_P2S,
-             stiff_scale=1.0, mass_scale=1.0) -> "Plan":
-        return Plan(self, terms(problem, material, precision, method, stiff_scale, mass_scale), orders, quad)
+             stiff_scale=1.0, mass_scale=1.0, output=OUTPUT_DENSE) -> "Plan":
+        return Plan(self, terms(problem, material, precision, method, stiff_scale, mass_scale, output), orders,
+                    quad)
 
 
 class Plan:
@@ -330,7 +334,7 @@ class Plan:
                                     _np_ptr(self.quad), ctypes.byref(h))
         ctx.check(rc, "p2s_plan_create")
         self._h = h
-        self.offsets = layout(t.problem, self.orders) if self.E else np.zeros(1, np.int64)
+        self.offsets = layout(t.problem, self.orders, t.output) if self.E else np.zeros(1, np.int64)
 
     @property
     def workspace_bytes(self) -> int:

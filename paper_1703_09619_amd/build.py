@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libp2s.so")
 
 HIP_SOURCES = ["p2s_api.hip", "p2s_kernels.hip", "p2s_contract.hip", "p2s_direct.hip", "p2s_direct_sf.hip",
-               "p2s_learned.hip", "p2s_split.hip", "p2s_cheb2d.hip"]
+               "p2s_learned.hip", "p2s_split.hip", "p2s_cheb2d.hip",
+               "p2s_contract_packed.hip"]
 CXX_SOURCES = ["p2s_tables.cpp"]
 ARCH = "gfx950"
 

@@ -192,6 +192,20 @@ int p2s_layout(int problem, int64_t E, const int32_t *orders, int64_t *offsets)
     return P2S_OK;
 }
 
+int p2s_layout_output(int problem, int output, int64_t E, const int32_t *orders, int64_t *offsets)
+{
+    if (output != P2S_OUTPUT_DENSE && output != P2S_OUTPUT_PACKED_UPPER) return P2S_EINVAL;
+    if (E < 0 || !offsets || (E > 0 && !orders)) return P2S_EINVAL;
+    if (problem != P2S_SCALAR && problem != P2S_VECTOR) return P2S_EINVAL;
+    offsets[0] = 0;
+    for (int64_t e = 0; e < E; ++e) {
+        const int64_t nd = p2s_num_dofs(problem, orders[e]);
+        if (nd < 0) return P2S_EORDER;
+        offsets[e + 1] = offsets[e] + (output == P2S_OUTPUT_DENSE ? nd * nd : nd * (nd + 1) / 2);
+    }
+    return P2S_OK;
+}
+
 int p2s_gauss_rule(int Q, double *x, double *w)
 {
     if (!x || !w) return P2S_EINVAL;
@@ -342,6 +356,11 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
         return fail(ctx, P2S_EINVAL, "plan: unsupported precision %d", terms->precision);
     if (terms->precision == P2S_SPLIT_FP32 && terms->method != P2S_METHOD_P2S)
         return fail(ctx, P2S_EINVAL, "plan: split-FP32 precision is a form of the product-to-sum method");
+    if (terms->output != P2S_OUTPUT_DENSE && terms->output != P2S_OUTPUT_PACKED_UPPER)
+        return fail(ctx, P2S_EINVAL, "plan: bad output layout %d", terms->output);
+    if (terms->output == P2S_OUTPUT_PACKED_UPPER &&
+        (terms->method != P2S_METHOD_P2S || terms->precision != P2S_FP64))
+        return fail(ctx, P2S_EINVAL, "plan: the packed output layout is written by the FP64 product-to-sum method");
     auto plan = new p2s_plan_s();
     plan->ctx = ctx;
     plan->terms = *terms;
@@ -376,7 +395,7 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
                       quad[3 * e + 2] != quad[2]))
             plan->uniform = false;
     }
-    p2s_layout(problem, E, orders, plan->offsets.data());
+    p2s_layout_output(problem, terms->output, E, orders, plan->offsets.data());
     if (E > 0) {
         plan->N = orders[0];
         plan->Qu = quad[0];
@@ -616,14 +635,16 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
             launch_contract_persistent(problem, plan->d_desc, plan->d_items + c.item0, c.nitem, plan->d_counter,
                                        plan->num_cu * plan->wpc, ctx->d_tab, plan->d_mom, out, status,
                                        plan->terms.stiff_scale, plan->terms.mass_scale, st);
-        } else if (plan->uniform) {
-            launch_contract(problem, plan->N, plan->d_desc, nullptr, c.e0, c.count, ctx->d_tab,
-                            plan->d_mom, out, status, plan->terms.stiff_scale, plan->terms.mass_scale, st);
         } else {
-            for (const auto &cl : c.classes)
-                launch_contract(problem, (int)cl[0], plan->d_desc, plan->d_elist, cl[1], cl[2], ctx->d_tab,
-                                plan->d_mom, out, status, plan->terms.stiff_scale,
-                                plan->terms.mass_scale, st);
+            const auto contract = plan->terms.output == P2S_OUTPUT_PACKED_UPPER ? launch_contract_packed
+                                                                                : launch_contract;
+            if (plan->uniform)
+                contract(problem, plan->N, plan->d_desc, nullptr, c.e0, c.count, ctx->d_tab, plan->d_mom, out,
+                         status, plan->terms.stiff_scale, plan->terms.mass_scale, st);
+            else
+                for (const auto &cl : c.classes)
+                    contract(problem, (int)cl[0], plan->d_desc, plan->d_elist, cl[1], cl[2], ctx->d_tab,
+                             plan->d_mom, out, status, plan->terms.stiff_scale, plan->terms.mass_scale, st);
         }
         prof_end(plan, 2, st);
     }
@@ -711,6 +732,7 @@ static bool same_shape(p2s_plan p, const p2s_terms *t, int64_t E, const int32_t 
     const p2s_terms &a = p->terms;
     return a.problem == t->problem && a.material == t->material && a.precision == t->precision &&
            a.method == t->method && a.stiff_scale == t->stiff_scale && a.mass_scale == t->mass_scale &&
+           a.output == t->output &&
            p->E == E && (E == 0 || (std::memcmp(p->orders.data(), orders, sizeof(int32_t) * E) == 0 &&
                                     std::memcmp(p->quad.data(), quad, sizeof(int32_t) * 3 * E) == 0));
 }
@@ -763,8 +785,8 @@ int p2s_fill_uniform_noalloc(p2s_ctx ctx, const p2s_terms *terms, int64_t E, int
     }
     if (problem == P2S_SCALAR && kind == P2S_MAT_ROTDIAG)
         return fail(ctx, P2S_EINVAL, "noalloc: the scalar problem takes an isotropic material");
-    if (terms->method != P2S_METHOD_P2S || terms->precision != P2S_FP64)
-        return fail(ctx, P2S_EINVAL, "noalloc: FP64 product-to-sum only");
+    if (terms->method != P2S_METHOD_P2S || terms->precision != P2S_FP64 || terms->output != P2S_OUTPUT_DENSE)
+        return fail(ctx, P2S_EINVAL, "noalloc: FP64 product-to-sum with the dense layout only");
     if (E < 0) return fail(ctx, P2S_EINVAL, "noalloc: negative E");
     if (N < 2 || N > P2S_MAX_ORDER) return fail(ctx, P2S_EORDER, "noalloc: order %d (allowed 2..%d)", N, P2S_MAX_ORDER);
     if (Qu < 1 || Qu > P2S_MAX_Q || Qv < 1 || Qv > P2S_MAX_Q || Qw < 1 || Qw > P2S_MAX_Q)
@@ -823,6 +845,8 @@ int p2s_plan_set_schedule(p2s_plan plan, int mode, int wgs_per_cu)
     if (mode != 0 && mode != 1) return fail(plan->ctx, P2S_EINVAL, "schedule: bad mode %d", mode);
     if (mode == 1 && plan->terms.problem != P2S_SCALAR)
         return fail(plan->ctx, P2S_EINVAL, "schedule: the persistent schedule is built for the scalar problem");
+    if (mode == 1 && plan->terms.output != P2S_OUTPUT_DENSE)
+        return fail(plan->ctx, P2S_EINVAL, "schedule: the persistent schedule writes the dense layout");
     if (mode == 1 && (wgs_per_cu < 1 || wgs_per_cu > 8))
         return fail(plan->ctx, P2S_EINVAL, "schedule: workgroups per CU must be 1..8");
     plan->mode = mode;
@@ -842,7 +866,7 @@ int p2s_plan_get_schedule(p2s_plan plan, int *mode, int *wgs_per_cu)
 static std::string plan_key(p2s_plan plan)
 {
     std::ostringstream k;
-    k << "gfx950/p" << plan->terms.problem << "/E" << plan->E << "/N";
+    k << "gfx950/p" << plan->terms.problem << "/o" << plan->terms.output << "/E" << plan->E << "/N";
     int hist[P2S_MAX_ORDER + 1] = {0};
     for (int n : plan->orders) hist[n]++;
     for (int n = 2; n <= P2S_MAX_ORDER; ++n)
@@ -911,7 +935,7 @@ int p2s_plan_autotune(p2s_plan plan, const double *nodes, const double *material
         }
     }
     std::vector<std::array<int, 2>> cand = {{0, 1}};
-    if (plan->terms.problem == P2S_SCALAR) {
+    if (plan->terms.problem == P2S_SCALAR && plan->terms.output == P2S_OUTPUT_DENSE) {
         cand.push_back({1, 1});
         cand.push_back({1, 2});
         cand.push_back({1, 4});

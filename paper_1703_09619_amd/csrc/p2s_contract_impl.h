@@ -202,7 +202,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t total_padded)
 // the moments are replaced by the coupling samples at the 2N-point rule
 // (mom = the sample buffer) and the linearization coefficients by the
 // weighted basis products w_a X_m1(x_a) Y_m2(x_a) at those points (dense).
-template <int PROB, int N, int I, int JB = I, int JE = num_comp(PROB), bool DSF = false>
+template <int PROB, int N, int I, int JB = I, int JE = num_comp(PROB), bool DSF = false, bool PACKED = false>
 __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int m1,
                                               const double *__restrict__ tab, const double *__restrict__ mom,
                                               double *__restrict__ out, uint32_t *__restrict__ status,
@@ -368,6 +368,24 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                 }
                 __syncthreads();
                 const int colj = comp_offset(PROB, N, J) + ma * CW;
+                if constexpr (PACKED) {
+                    // packed upper triangle: row rg holds columns cg >= rg at
+                    // rg NDOF - rg (rg - 1) / 2 + (cg - rg); no mirror
+                    const int dr = nthreads / W, dc = nthreads - dr * W;
+                    int r = tid / W, c = tid - r * W;
+                    while (r < NR) {
+                        const int64_t rg = rowbase + r, cg = colj + c;
+                        if (cg >= rg) obase[rg * NDOF - rg * (rg - 1) / 2 + (cg - rg)] = smem[r * WS + c];
+                        r += dr;
+                        c += dc;
+                        if (c >= W) {
+                            c -= W;
+                            ++r;
+                        }
+                    }
+                    __syncthreads();
+                    continue;
+                }
                 // mirrored rows start after the diagonal slab m2 == m1 of block (I,I)
                 const int cmir = (J == I && ma == m2lo) ? CW : 0;
                 double *drow = obase + (int64_t)rowbase * NDOF + colj;
@@ -449,7 +467,7 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
 // single block, which keeps it within the instruction cache (a kernel with
 // all three column blocks of I = 0 missed in it two orders of magnitude more
 // often than one with a single block).
-template <int PROB, int N, int I, int J, bool DSF = false>
+template <int PROB, int N, int I, int J, bool DSF = false, bool PACKED = false>
 __global__ __launch_bounds__((CS<PROB, N, I, J, J + 1, DSF>::THREADS), (N <= 6 ? 3 : 2)) void k_contract(
     const ElemDesc *__restrict__ desc, const int32_t *__restrict__ elist, int64_t e0, int64_t nitems,
     int64_t padded, const double *__restrict__ tab, const double *__restrict__ mom,
@@ -463,10 +481,10 @@ __global__ __launch_bounds__((CS<PROB, N, I, J, J + 1, DSF>::THREADS), (N <= 6 ?
     const int m1 = (int)(item % S::NM_I);
     const ElemDesc d = desc[e];
     __shared__ __attribute__((aligned(16))) double smem[S::BUF];
-    contract_item<PROB, N, I, J, J + 1, DSF>(d, e, m1, tab, mom, out, status, sK, sM, smem, S::THREADS);
+    contract_item<PROB, N, I, J, J + 1, DSF, PACKED>(d, e, m1, tab, mom, out, status, sK, sM, smem, S::THREADS);
 }
 
-template <int PROB, int N, int I, int J, bool DSF = false>
+template <int PROB, int N, int I, int J, bool DSF = false, bool PACKED = false>
 static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,
                               const double *tab, const double *mom, double *out, uint32_t *status,
                               double sK, double sM, hipStream_t st)
@@ -474,23 +492,23 @@ static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_
     using S = CS<PROB, N, I, J, J + 1, DSF>;
     const int64_t nitems = count * S::NM_I;
     const int64_t padded = (nitems + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_contract<PROB, N, I, J, DSF>), dim3((unsigned)padded), dim3(S::THREADS), 0, st, desc,
+    hipLaunchKernelGGL((k_contract<PROB, N, I, J, DSF, PACKED>), dim3((unsigned)padded), dim3(S::THREADS), 0, st, desc,
                        elist, e0, nitems, padded, tab, mom, out, status, sK, sM);
 }
 
 // The blocks (I, J >= I) of one problem and order, one launch each.
-template <int PROB, int N, bool DSF = false>
+template <int PROB, int N, bool DSF = false, bool PACKED = false>
 static void launch_contract_t(const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,
                               const double *tab, const double *mom, double *out, uint32_t *status,
                               double sK, double sM, hipStream_t st)
 {
-    launch_contract_i<PROB, N, 0, 0, DSF>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+    launch_contract_i<PROB, N, 0, 0, DSF, PACKED>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
     if constexpr (PROB == 1) {
-        launch_contract_i<PROB, N, 0, 1, DSF>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
-        launch_contract_i<PROB, N, 0, 2, DSF>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
-        launch_contract_i<PROB, N, 1, 1, DSF>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
-        launch_contract_i<PROB, N, 1, 2, DSF>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
-        launch_contract_i<PROB, N, 2, 2, DSF>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+        launch_contract_i<PROB, N, 0, 1, DSF, PACKED>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+        launch_contract_i<PROB, N, 0, 2, DSF, PACKED>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+        launch_contract_i<PROB, N, 1, 1, DSF, PACKED>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+        launch_contract_i<PROB, N, 1, 2, DSF, PACKED>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
+        launch_contract_i<PROB, N, 2, 2, DSF, PACKED>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
     }
 }
 

@@ -36,6 +36,12 @@ int launch_contract(int problem, int N, const ElemDesc *desc, const int32_t *eli
                     int64_t count, const double *tab, const double *mom, double *out, uint32_t *status,
                     double sK, double sM, hipStream_t st);
 
+// The same contraction writing each element's upper triangle, packed row by
+// row (p2s_contract_packed.hip).
+int launch_contract_packed(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,
+                           const double *tab, const double *mom, double *out, uint32_t *status, double sK, double sM,
+                           hipStream_t st);
+
 // Sum-factorized direct quadrature (p2s_direct_sf.hip): the contraction's
 // three stages over the coupling samples alpha (rules of 2N points per axis).
 int launch_contract_dsf(int problem, int N, const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,

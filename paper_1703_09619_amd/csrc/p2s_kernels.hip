@@ -401,8 +401,9 @@ __device__ void moments_body(const ElemDesc &d, int64_t e, int f, int F, const d
             if (lane == 0) sm[wave * TAIL_REC + i] = v;
         }
         __syncthreads();
-        if (tid < 15) {
-            // scale of every reduced axis: the largest moment magnitude
+        if (tid < TAIL_REC) {
+            // scale of every reduced axis: the largest moment magnitude;
+            // entry 15 is unused and written as zero
             const int src = tid >= 12 ? 12 : tid;
             const bool on = tid < 12 || (tid == 12 && tu) || (tid == 13 && tv) || (tid == 14 && tw);
             double v = 0.0;

@@ -485,3 +485,34 @@ def test_direct_sf_rule_restriction(env):
         ctx.plan(0, 0, [4], [[8, 8, 7]], method=p2s.METHOD_DIRECT_SF)
     with pytest.raises(p2s.P2SError, match="FP64"):
         ctx.plan(1, 1, [4], [[8, 8, 8]], method=p2s.METHOD_DIRECT_SF, precision=p2s.SPLIT_FP32)
+
+
+@pytest.mark.parametrize("name,E", [("vector_n6", 40), ("scalar_mixed", 150), ("scalar_n4", 64)])
+def test_packed_upper_output(env, name, E):
+    """Packed symmetric output (upper triangle, row by row): every packed
+    entry equals the dense fill's entry bit for bit (the same kernels write
+    both; the packed form skips the mirrored half)."""
+    torch, W, p2s = env["torch"], env["W"], env["p2s"]
+    w = W.make(name, E=E)
+    nodes, mat = torch.from_numpy(w.nodes).cuda(), torch.from_numpy(w.mat).cuda()
+    dense_plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad)
+    pk_plan = env["ctx"].plan(w.problem, w.material, w.orders, w.quad, output=p2s.OUTPUT_PACKED_UPPER)
+    dense, sd = dense_plan.execute(nodes, mat)
+    packed = torch.full((int(pk_plan.offsets[-1]),), float("nan"), dtype=torch.float64, device="cuda")
+    sp = torch.empty_like(sd)
+    pk_plan.execute(nodes, mat, packed, sp)
+    torch.cuda.synchronize()
+    assert torch.equal(sd, sp)
+    d, p = dense.cpu().numpy(), packed.cpu().numpy()
+    for e in range(w.E):
+        n = p2s.num_dofs(w.problem, int(w.orders[e]))
+        A = d[dense_plan.offsets[e]:dense_plan.offsets[e + 1]].reshape(n, n)
+        iu = np.triu_indices(n)
+        got = p[pk_plan.offsets[e]:pk_plan.offsets[e + 1]]
+        assert got.size == n * (n + 1) // 2
+        assert np.array_equal(got, A[iu]), e
+    with pytest.raises(p2s.P2SError):
+        pk_plan.set_schedule(1, 1)
+    with pytest.raises(p2s.P2SError, match="packed"):
+        env["ctx"].plan(w.problem, w.material, w.orders, w.quad, output=p2s.OUTPUT_PACKED_UPPER,
+                        method=p2s.METHOD_DIRECT)

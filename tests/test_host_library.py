@@ -50,6 +50,14 @@ def test_num_dofs_and_layout(p2s):
         p2s.layout(p2s.VECTOR, [6, 11])
 
 
+def test_packed_layout(p2s):
+    off = p2s.layout(p2s.VECTOR, [6, 2, 3], p2s.OUTPUT_PACKED_UPPER)
+    sizes = [540 * 541 // 2, 12 * 13 // 2, 54 * 55 // 2]
+    assert off.tolist() == [0, sizes[0], sizes[0] + sizes[1], sum(sizes)]
+    with pytest.raises(p2s.P2SError):
+        p2s.layout(p2s.SCALAR, [3], 7)
+
+
 def test_create_without_device_fails_cleanly(p2s):
     import torch
     if torch.cuda.is_available():
