@@ -145,7 +145,7 @@ def cpu_model() -> str:
 def contraction_kernel_name(w, split, schedule):
     uniform = len(set(w.orders.tolist())) == 1
     if split:
-        return "k_contract_split<%d,I,J> (blocks J >= I)" % w.problem, 6 if w.problem else 1
+        return "k_contract_split<%d,I,J,I8> (blocks J >= I)" % w.problem, 6 if w.problem else 1
     if not uniform and schedule and schedule["mode"] == "persistent":
         return "k_contract_persistent_scalar", 1
     if not uniform:
@@ -153,12 +153,13 @@ def contraction_kernel_name(w, split, schedule):
     return "k_contract<%d,%d,I,J> (blocks J >= I)" % (w.problem, int(w.orders[0])), 6 if w.problem else 1
 
 
-def timed_fill(torch, p2s, ctx, w, steps, warmup, split=False, learned=None, out=None):
+def timed_fill(torch, p2s, ctx, w, steps, warmup, split=False, learned=None, out=None, int8=False):
     """Plan + warm-up + `steps` timed executions of workload w.  Returns
     (info, plan, out, status): info holds ms per step, the stage times (HIP
     events on the launch stream) and the contraction stage's roofline."""
     dev = torch.device("cuda", 0)
-    plan = ctx.plan(w.problem, w.material, w.orders, w.quad, precision=p2s.SPLIT_FP32 if split else p2s.FP64)
+    prec = (p2s.SPLIT_INT8 if int8 else p2s.SPLIT_FP32) if split else p2s.FP64
+    plan = ctx.plan(w.problem, w.material, w.orders, w.quad, precision=prec)
     if learned is not None:
         plan.set_learned(True, learned["p_cover"], learned["theta"], learned.get("k_direct", p2s.KMAX + 1))
     nodes = torch.from_numpy(w.nodes).to(dev)
@@ -274,9 +275,20 @@ def compact_configs(torch, p2s, ctx, W, oracle, steps, warmup, log):
         "stages_ms_per_step": info["stages_ms_per_step"], "max_rel_err_vs_oracle": es, "oracle_elements": 1,
         "max_rel_err_vs_fp64_gpu": float(e_vs64.max()), "fp64_gpu_elements": n64,
         "speedup_vs_fp64": round(res["vector_n8_fp64"]["ms_per_step"] / info["ms_per_step"], 3)}
+    del plan
+    log("vector_n8 split done")
+    info, plan, out, st = timed_fill(torch, p2s, ctx, w, max(3, steps // 2), 1, split=True, out=out, int8=True)
+    ei = float(np.linalg.norm(out[:int(roff[1])].cpu().numpy() - ref) / np.linalg.norm(ref))
+    e_vs64 = ctx.rel_error(out[:int(plan.offsets[n64])], keep64, offsets=off64).cpu().numpy()
+    res["vector_n8_split_int8"] = {
+        "elements": w.E, "value": round(info["value"], 1), "unit": "element matrices/s",
+        "ms_per_step": round(info["ms_per_step"], 4), "roofline_frac": info["roofline"]["frac"], "bound": "hbm",
+        "stages_ms_per_step": info["stages_ms_per_step"], "max_rel_err_vs_oracle": ei, "oracle_elements": 1,
+        "max_rel_err_vs_fp64_gpu": float(e_vs64.max()), "fp64_gpu_elements": n64,
+        "speedup_vs_fp64": round(res["vector_n8_fp64"]["ms_per_step"] / info["ms_per_step"], 3)}
     del plan, out, keep64
     torch.cuda.empty_cache()
-    log("vector_n8 split done")
+    log("vector_n8 split int8 done")
     # learned order against the full rule on the same 50000 elements
     from paper_1703_09619_amd import learned_k
     meta = json.load(open(os.path.splitext(learned_k.DEFAULT_MODEL)[0] + ".json"))
@@ -390,7 +402,7 @@ def main():
     ap.add_argument("--direct-elements", type=int, default=64,
                     help="elements of the same workload filled by the GPU direct-quadrature baseline "
                          "(0 = skip)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "split_fp32"],
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "split_fp32", "split_int8"],
                     help="arithmetic of the moment and contraction stages; split_fp32 also times the FP64 "
                          "path on the same inputs and reports the split error against it")
     ap.add_argument("--copy-probe", action="store_true",
@@ -412,7 +424,8 @@ def main():
     w = W.make(args.workload)
     dev = torch.device("cuda", 0)
     ctx = p2s.Context(0)
-    split = args.precision == "split_fp32"
+    split = args.precision in ("split_fp32", "split_int8")
+    int8 = args.precision == "split_int8"
     learned = None
     if args.workload == "scalar_planewave":
         from paper_1703_09619_amd import learned_k
@@ -427,7 +440,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    info, plan, out, status = timed_fill(torch, p2s, ctx, w, args.steps, args.warmup, split=split, learned=learned)
+    info, plan, out, status = timed_fill(torch, p2s, ctx, w, args.steps, args.warmup, split=split, learned=learned,
+                                         int8=int8)
     nodes, mat = info["nodes"], info["mat"]
     ms_per_step = info["ms_per_step"]
     value = info["value"]
@@ -471,14 +485,15 @@ def main():
         e64 = ctx.rel_error(out[:int(p64.offsets[-1])], o64,
                             offsets=torch.from_numpy(p64.offsets).to(dev)).cpu().numpy()
         del o64
-        precision = {"form": "split_fp32", "elements_compared": n64,
+        precision = {"form": args.precision, "elements_compared": n64,
                      "max_rel_err_vs_fp64_gpu": float(e64.max()), "mean_rel_err_vs_fp64_gpu": float(e64.mean())}
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "element matrices/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 MFMA on exact 10-bit operand slices + f64" if split else "f64",
+        "dtype": ("i8 MFMA on exact 7-bit operand slices + f64" if int8 else
+                  "f32 MFMA on exact 10-bit operand slices + f64") if split else "f64",
         "data": "synthetic (seeded curved triquadratic hexahedra and analytic materials)",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "elements": w.E,
                    "orders": sorted(set(int(n) for n in w.orders)), "gauss_points": w.quad[0].tolist(),

@@ -96,7 +96,10 @@ typedef enum {
  * added into FP64), with map/Jacobian/coupling/tables, intermediates and
  * every sum in FP64.  Relative error about 1e-11.  Uniform plans with at
  * most 16 Gauss points per axis (P2S_EQUAD otherwise). */
-typedef enum { P2S_FP64 = 0, P2S_SPLIT_FP32 = 1 } p2s_precision;
+/* P2S_SPLIT_INT8: the same exact-slice products on the INT8 matrix cores
+ * (v_mfma_i32_16x16x32_i8): per K-block of 16, six 7-bit slices per operand,
+ * slice orders up to 5, exact int32 sums added into FP64; same limits. */
+typedef enum { P2S_FP64 = 0, P2S_SPLIT_FP32 = 1, P2S_SPLIT_INT8 = 2 } p2s_precision;
 
 /* Method: product-to-sum (the paper's method, Section II eqs. (3)-(4)),
  * or one of two GPU baselines computing the same discrete matrix of eq. (2):

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libp2s.so")
 
 SCALAR, VECTOR = 0, 1
 MAT_SINCOSEXP, MAT_ROTDIAG, MAT_PLANEWAVE, ALPHA_SAMPLED = 0, 1, 2, 3
-FP64, SPLIT_FP32 = 0, 1
+FP64, SPLIT_FP32, SPLIT_INT8 = 0, 1, 2
 METHOD_P2S, METHOD_DIRECT, METHOD_DIRECT_SF = 0, 1, 2
 OUTPUT_DENSE, OUTPUT_PACKED_UPPER = 0, 1
 FAM_PHI, FAM_DPHI, FAM_PSI = 0, 1, 2

@@ -352,10 +352,11 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
                 return fail(ctx, P2S_EQUAD, "plan: sum-factorized direct quadrature takes rules of 2N Gauss points "
                                             "per axis (element %lld: order %d)", (long long)e, orders[e]);
     }
-    if (terms->precision != P2S_FP64 && terms->precision != P2S_SPLIT_FP32)
+    if (terms->precision != P2S_FP64 && terms->precision != P2S_SPLIT_FP32 && terms->precision != P2S_SPLIT_INT8)
         return fail(ctx, P2S_EINVAL, "plan: unsupported precision %d", terms->precision);
-    if (terms->precision == P2S_SPLIT_FP32 && terms->method != P2S_METHOD_P2S)
-        return fail(ctx, P2S_EINVAL, "plan: split-FP32 precision is a form of the product-to-sum method");
+    if (terms->precision != P2S_FP64 && terms->method != P2S_METHOD_P2S)
+        return fail(ctx, P2S_EINVAL, "plan: split-FP32 and split-INT8 precision are forms of the product-to-sum "
+                                     "method");
     if (terms->output != P2S_OUTPUT_DENSE && terms->output != P2S_OUTPUT_PACKED_UPPER)
         return fail(ctx, P2S_EINVAL, "plan: bad output layout %d", terms->output);
     if (terms->output == P2S_OUTPUT_PACKED_UPPER &&
@@ -410,11 +411,11 @@ int p2s_plan_create(p2s_ctx ctx, const p2s_terms *terms, int64_t E, const int32_
         delete plan;
         return fail(ctx, P2S_EINVAL, "plan: sampled coupling input needs one order and rule for all elements");
     }
-    if (terms->precision == P2S_SPLIT_FP32 && E > 0 &&
+    if (terms->precision != P2S_FP64 && E > 0 &&
         (!plan->uniform || plan->Qu > SPLIT_MAXQ || plan->Qv > SPLIT_MAXQ || plan->Qw > SPLIT_MAXQ)) {
         delete plan;
-        return fail(ctx, P2S_EQUAD, "plan: split-FP32 precision takes one order and one rule of at most %d points "
-                                    "per axis for all elements", SPLIT_MAXQ);
+        return fail(ctx, P2S_EQUAD, "plan: split-FP32 and split-INT8 precision take one order and one rule of at "
+                                    "most %d points per axis for all elements", SPLIT_MAXQ);
     }
     if (E > 0 && (moments_lds_bytes(plan->mshape) > LDS_LIMIT ||
                   moments_smem_bytes(plan->maxN, plan->mshape.maxQw, plan->mshape.maxQvw) > LDS_LIMIT)) {
@@ -593,10 +594,12 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
                                         hipMemcpyDeviceToDevice, st));
             continue;
         }
-        const bool split = plan->terms.precision == P2S_SPLIT_FP32;
+        const bool split = plan->terms.precision != P2S_FP64;
+        const bool int8 = plan->terms.precision == P2S_SPLIT_INT8;
         prof_begin(plan, 1, st);
         if (split && stop != STOP_TAILREC)
-            launch_moments_split(problem, plan->d_desc, c.e0, c.count, plan->d_alpha, ctx->d_tab, plan->d_mom, st);
+            launch_moments_split(problem, plan->d_desc, c.e0, c.count, plan->d_alpha, ctx->d_tab, plan->d_mom, int8,
+                                 st);
         else if (!plan->uniform && !learned && stop != STOP_TAILREC)
             // mixed orders: one launch per order class, each with the LDS
             // shape of its own elements rather than of the largest order
@@ -630,7 +633,7 @@ static int run_plan(p2s_plan plan, const double *nodes, const double *material, 
         prof_begin(plan, 2, st);
         if (split) {
             launch_contract_split(problem, plan->N, plan->d_desc, c.e0, c.count, ctx->d_tab, plan->d_mom, out, status,
-                                  plan->terms.stiff_scale, plan->terms.mass_scale, st);
+                                  plan->terms.stiff_scale, plan->terms.mass_scale, int8, st);
         } else if (plan->mode == 1) {
             launch_contract_persistent(problem, plan->d_desc, plan->d_items + c.item0, c.nitem, plan->d_counter,
                                        plan->num_cu * plan->wpc, ctx->d_tab, plan->d_mom, out, status,

@@ -56,10 +56,13 @@ int launch_contract_persistent(int problem, const ElemDesc *desc, const WorkItem
 // Split-FP32 form of the moment stage and the contraction (p2s_split.hip):
 // FP32 matrix-core products on exact operand slices, FP64 sums; FP64
 // moments at mom + mom_off; uniform plans, Q <= 16.
+// int8: the products on the INT8 matrix cores (seven-bit slices) instead of
+// the FP32 ones.
 void launch_moments_split(int problem, const ElemDesc *desc, int64_t e0, int64_t count, const double *alpha,
-                          const double *tab, double *mom, hipStream_t st);
+                          const double *tab, double *mom, bool int8, hipStream_t st);
 void launch_contract_split(int problem, int N, const ElemDesc *desc, int64_t e0, int64_t count, const double *tab,
-                           const double *mom, double *out, uint32_t *status, double sK, double sM, hipStream_t st);
+                           const double *mom, double *out, uint32_t *status, double sK, double sM, bool int8,
+                           hipStream_t st);
 int prepare_split_kernels();
 
 // Direct quadrature of eq. (2) (baseline method), from coupling samples.

@@ -78,6 +78,95 @@ __device__ __forceinline__ void exact_step(double a, double b, double (&acc)[4])
     }
 }
 
+// The same product on the INT8 matrix cores (v_mfma_i32_16x16x32_i8) for a
+// whole K-block of 16: this lane holds a[j] = A[r16][4j + k4] and
+// b[j] = B[4j + k4][r16], j = 0..3.  Rows of A and columns of B take one
+// power-of-two scale over the block and six signed 7-bit slices,
+// x 2^-e = 2^-6 sum_p s_p 2^(-7p), |s_p| <= 64.  Level l = p + q collects
+// the products s_p t_q; one 16x16x32 instruction holds two slice pairs
+// (p, q) for the 16 values of k (each lane supplies its own four k for both
+// pairs, so no operand crosses lanes), and its int32 sum of at most 32
+// products below 2^12 is exact.  Levels 0..5 take 12 instructions; the
+// dropped levels are below 2^-42 of the row and column scales.
+typedef int i4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ i4 mfma_i8(long a, long b, i4 c)
+{
+    return __builtin_amdgcn_mfma_i32_16x16x32_i8(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void slices6(double x, int (&s)[6])
+{
+    double t = x * 64.0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const double a = rint(t);
+        s[p] = (int)a;
+        t = (t - a) * 128.0;
+    }
+}
+
+__device__ __forceinline__ long pack8(int b0, int b1, int b2, int b3, int b4, int b5, int b6, int b7)
+{
+    const unsigned lo = (unsigned)(b0 & 255) | ((unsigned)(b1 & 255) << 8) | ((unsigned)(b2 & 255) << 16) |
+                        ((unsigned)(b3 & 255) << 24);
+    const unsigned hi = (unsigned)(b4 & 255) | ((unsigned)(b5 & 255) << 8) | ((unsigned)(b6 & 255) << 16) |
+                        ((unsigned)(b7 & 255) << 24);
+    return (long)(((unsigned long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ void exact_block_i8(const double (&a)[4], const double (&b)[4], double (&acc)[4])
+{
+    const int k4 = (threadIdx.x & 63) >> 4;
+    double ma = fmax(fmax(fabs(a[0]), fabs(a[1])), fmax(fabs(a[2]), fabs(a[3])));
+    double mb = fmax(fmax(fabs(b[0]), fabs(b[1])), fmax(fabs(b[2]), fabs(b[3])));
+    ma = fmax(ma, __shfl_xor(ma, 16, 64));
+    ma = fmax(ma, __shfl_xor(ma, 32, 64));
+    mb = fmax(mb, __shfl_xor(mb, 16, 64));
+    mb = fmax(mb, __shfl_xor(mb, 32, 64));
+    int ea = 0, eb = 0;
+    (void)frexp(ma, &ea);
+    (void)frexp(mb, &eb);
+    int sa[4][6], sb[4][6];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        slices6(ldexp(a[j], -ea), sa[j]);
+        slices6(ldexp(b[j], -eb), sb[j]);
+    }
+    int er[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) er[i] = __shfl(ea, 4 * k4 + i, 64);  // exponent of result row 4 k4 + i
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        i4 c = {0, 0, 0, 0};
+#pragma unroll
+        for (int p = 0; p <= l; p += 2) {
+            // bytes 0..3: pair (p, l-p); bytes 4..7: pair (p+1, l-p-1) (zero past l)
+            const bool two = p + 1 <= l;
+            const long pa = pack8(sa[0][p], sa[1][p], sa[2][p], sa[3][p], two ? sa[0][p + 1] : 0,
+                                  two ? sa[1][p + 1] : 0, two ? sa[2][p + 1] : 0, two ? sa[3][p + 1] : 0);
+            const long pb = pack8(sb[0][l - p], sb[1][l - p], sb[2][l - p], sb[3][l - p], two ? sb[0][l - p - 1] : 0,
+                                  two ? sb[1][l - p - 1] : 0, two ? sb[2][l - p - 1] : 0,
+                                  two ? sb[3][l - p - 1] : 0);
+            c = mfma_i8(pa, pb, c);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += ldexp((double)c[i], er[i] + eb - 12 - 7 * l);
+    }
+}
+
+// One K-block of 16 of D += A B: a[j] = A[r16][4j + k4], b[j] = B[4j + k4][r16].
+template <bool I8>
+__device__ __forceinline__ void exact_block(const double (&a)[4], const double (&b)[4], double (&acc)[4])
+{
+    if constexpr (I8) {
+        exact_block_i8(a, b, acc);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) exact_step(a[j], b[j], acc);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Moments: one workgroup (4 waves) per (element, field); Q <= 16 per axis,
 // K = 2N-1 <= 15.  Three GEMM passes, each one K-block of 16 (four steps):
@@ -89,6 +178,7 @@ __device__ __forceinline__ void exact_step(double a, double b, double (&acc)[4])
 constexpr int PS = 17;  // LDS row stride of the pass results (doubles)
 constexpr size_t MOMENTS_SPLIT_LDS = sizeof(double) * 2 * 256 * PS;
 
+template <bool I8>
 __global__ __launch_bounds__(256) void k_moments_split(const ElemDesc *__restrict__ desc, int64_t e0,
                                                        const double *__restrict__ alpha,
                                                        const double *__restrict__ tab, double *__restrict__ mom)
@@ -112,12 +202,14 @@ __global__ __launch_bounds__(256) void k_moments_split(const ElemDesc *__restric
     for (int mt = wave; mt < 16; mt += 4) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         const int ab = mt * 16 + r16;
+        double xa[4], xb[4];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int cc = ks * 4 + k4;
-            const double x = (ab < nab && cc < Qw) ? A[(int64_t)ab * Qw + cc] : 0.0;
-            exact_step(x, Ww[r16 * MAXQ + cc], acc);
+            xa[ks] = (ab < nab && cc < Qw) ? A[(int64_t)ab * Qw + cc] : 0.0;
+            xb[ks] = Ww[r16 * MAXQ + cc];
         }
+        exact_block<I8>(xa, xb, acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) P1[(mt * 16 + 4 * k4 + i) * PS + r16] = acc[i];
     }
@@ -125,12 +217,14 @@ __global__ __launch_bounds__(256) void k_moments_split(const ElemDesc *__restric
     // pass 2: per a, M = l, K = b, N = q
     for (int a = wave; a < Qu; a += 4) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double xa[4], xb[4];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int b = ks * 4 + k4;
-            const double x = b < Qv ? P1[(a * Qv + b) * PS + r16] : 0.0;
-            exact_step(Wv[r16 * MAXQ + b], x, acc);
+            xa[ks] = Wv[r16 * MAXQ + b];
+            xb[ks] = b < Qv ? P1[(a * Qv + b) * PS + r16] : 0.0;
         }
+        exact_block<I8>(xa, xb, acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) P2[(a * 16 + 4 * k4 + i) * PS + r16] = acc[i];
     }
@@ -139,12 +233,14 @@ __global__ __launch_bounds__(256) void k_moments_split(const ElemDesc *__restric
     double *I = mom + d.mom_off + (int64_t)f * K * K * K;
     for (int nt = wave; nt < 16; nt += 4) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double xa[4], xb[4];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int a = ks * 4 + k4;
-            const double x = a < Qu ? P2[(a * 16 + nt) * PS + r16] : 0.0;
-            exact_step(Wu[r16 * MAXQ + a], x, acc);
+            xa[ks] = Wu[r16 * MAXQ + a];
+            xb[ks] = a < Qu ? P2[(a * 16 + nt) * PS + r16] : 0.0;
         }
+        exact_block<I8>(xa, xb, acc);
         const int l = nt, q = r16;
         if (l < K && q < K)
 #pragma unroll
@@ -181,7 +277,7 @@ constexpr size_t contract_split_lds()
                              (NG <= SPLIT_TILED_MAXG ? 64 * SPLIT_TILE_STRIDE : 0));
 }
 
-template <int PROB, int I, int J>
+template <int PROB, int I, int J, bool I8>
 __global__ __launch_bounds__(256) void k_contract_split(const ElemDesc *__restrict__ desc, int64_t e0, int64_t count,
                                                         int64_t total_padded, const double *__restrict__ tab,
                                                         const double *__restrict__ mom, double *__restrict__ out,
@@ -223,15 +319,15 @@ __global__ __launch_bounds__(256) void k_contract_split(const ElemDesc *__restri
                 constexpr TermC t = BK.t[decltype(sc_)::value];
                 const double sc = (t.scale ? sM : sK) * (double)t.sign;
                 const double *Is = Im + (int64_t)t.field * K * K * K;
+                double xa[4], xb[4];
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) {
                     const int k = ks * 4 + k4;
                     const int m2 = r16 < MAXN ? r16 : MAXN - 1;  // rows 8..15 are padding
-                    const double a =
-                        r16 < MAXN ? sc * LIN[t.tu * LIN_STRIDE_T + m1 * LIN_STRIDE_M1 + m2 * KPAD + k] : 0.0;
-                    const double x = (k < K && nt < K && r16 < K) ? Is[(k * K + nt) * K + r16] : 0.0;
-                    exact_step(a, x, acc);
+                    xa[ks] = r16 < MAXN ? sc * LIN[t.tu * LIN_STRIDE_T + m1 * LIN_STRIDE_M1 + m2 * KPAD + k] : 0.0;
+                    xb[ks] = (k < K && nt < K && r16 < K) ? Is[(k * K + nt) * K + r16] : 0.0;
                 }
+                exact_block<I8>(xa, xb, acc);
             });
             if (k4 < 2)
 #pragma unroll
@@ -255,11 +351,15 @@ __global__ __launch_bounds__(256) void k_contract_split(const ElemDesc *__restri
             constexpr int tv = BK.t[BK.gstart[g]].tv;
             constexpr int tw = BK.t[BK.gstart[g]].tw;
             // stage B for group g, accumulated over the run
+            {
+                double xa[4], xb[4];
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int l = ks * 4 + k4;
-                const double c = LIN[tv * LIN_STRIDE_T + bn1 * LIN_STRIDE_M1 + bn2 * KPAD + l];
-                exact_step(c, Ag[(g * 8 + m2) * 256 + l * 16 + r16], cb);
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int l = ks * 4 + k4;
+                    xa[ks] = LIN[tv * LIN_STRIDE_T + bn1 * LIN_STRIDE_M1 + bn2 * KPAD + l];
+                    xb[ks] = Ag[(g * 8 + m2) * 256 + l * 16 + r16];
+                }
+                exact_block<I8>(xa, xb, cb);
             }
             if constexpr (BK.cflag[g] != 0) {
                 // transpose the wave's Bsum tile for use as the A operand
@@ -273,12 +373,14 @@ __global__ __launch_bounds__(256) void k_contract_split(const ElemDesc *__restri
                     const int pp = nt * 16 + r16;
                     const int p1 = pp >> 3, p2 = pp & 7;
                     double cc[4] = {0.0, 0.0, 0.0, 0.0};
+                    double xa[4], xb[4];
 #pragma unroll
                     for (int ks = 0; ks < 4; ++ks) {
                         const int q = ks * 4 + k4;
-                        exact_step(bt[r16 * PS + q], LIN[tw * LIN_STRIDE_T + p1 * LIN_STRIDE_M1 + p2 * KPAD + q],
-                                   cc);
+                        xa[ks] = bt[r16 * PS + q];
+                        xb[ks] = LIN[tw * LIN_STRIDE_T + p1 * LIN_STRIDE_M1 + p2 * KPAD + q];
                     }
+                    exact_block<I8>(xa, xb, cc);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) acc[nt * 4 + i] += cc[i];
                 }
@@ -338,61 +440,80 @@ __global__ __launch_bounds__(256) void k_contract_split(const ElemDesc *__restri
 // ---------------------------------------------------------------------------
 
 void launch_moments_split(int problem, const ElemDesc *desc, int64_t e0, int64_t count, const double *alpha,
-                          const double *tab, double *mom, hipStream_t st)
+                          const double *tab, double *mom, bool int8, hipStream_t st)
 {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_moments_split, dim3((unsigned)count, num_fields(problem)), dim3(256), MOMENTS_SPLIT_LDS, st,
-                       desc, e0, alpha, tab, mom);
+    if (int8)
+        hipLaunchKernelGGL(k_moments_split<true>, dim3((unsigned)count, num_fields(problem)), dim3(256),
+                           MOMENTS_SPLIT_LDS, st, desc, e0, alpha, tab, mom);
+    else
+        hipLaunchKernelGGL(k_moments_split<false>, dim3((unsigned)count, num_fields(problem)), dim3(256),
+                           MOMENTS_SPLIT_LDS, st, desc, e0, alpha, tab, mom);
 }
 
-template <int PROB, int I, int J>
+template <int PROB, int I, int J, bool I8>
 static void launch_block(int N, const ElemDesc *desc, int64_t e0, int64_t count, const double *tab,
                          const double *mom, double *out, uint32_t *status, double sK, double sM, hipStream_t st)
 {
     const int64_t items = count * comp_dim(PROB, N, I, 0);
     const int64_t padded = (items + 7) & ~int64_t(7);
     constexpr size_t lds = contract_split_lds<BlockOf<PROB, I, J>::B.ngroup>();
-    hipLaunchKernelGGL((k_contract_split<PROB, I, J>), dim3((unsigned)padded), dim3(256), lds, st, desc, e0, count,
-                       padded, tab, mom, out, status, sK, sM);
+    hipLaunchKernelGGL((k_contract_split<PROB, I, J, I8>), dim3((unsigned)padded), dim3(256), lds, st, desc, e0,
+                       count, padded, tab, mom, out, status, sK, sM);
+}
+
+template <bool I8>
+static void launch_split_blocks(int problem, int N, const ElemDesc *desc, int64_t e0, int64_t count,
+                                const double *tab, const double *mom, double *out, uint32_t *status, double sK,
+                                double sM, hipStream_t st)
+{
+    if (problem == 0) {
+        launch_block<0, 0, 0, I8>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
+        return;
+    }
+    launch_block<1, 0, 0, I8>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
+    launch_block<1, 0, 1, I8>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
+    launch_block<1, 0, 2, I8>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
+    launch_block<1, 1, 1, I8>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
+    launch_block<1, 1, 2, I8>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
+    launch_block<1, 2, 2, I8>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
 }
 
 void launch_contract_split(int problem, int N, const ElemDesc *desc, int64_t e0, int64_t count, const double *tab,
-                           const double *mom, double *out, uint32_t *status, double sK, double sM, hipStream_t st)
+                           const double *mom, double *out, uint32_t *status, double sK, double sM, bool int8,
+                           hipStream_t st)
 {
     if (count <= 0) return;
-    if (problem == 0) {
-        launch_block<0, 0, 0>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
-        return;
-    }
-    launch_block<1, 0, 0>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
-    launch_block<1, 0, 1>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
-    launch_block<1, 0, 2>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
-    launch_block<1, 1, 1>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
-    launch_block<1, 1, 2>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
-    launch_block<1, 2, 2>(N, desc, e0, count, tab, mom, out, status, sK, sM, st);
+    if (int8)
+        launch_split_blocks<true>(problem, N, desc, e0, count, tab, mom, out, status, sK, sM, st);
+    else
+        launch_split_blocks<false>(problem, N, desc, e0, count, tab, mom, out, status, sK, sM, st);
 }
 
-template <int PROB, int I, int J>
+template <int PROB, int I, int J, bool I8>
 static int allow_lds()
 {
     constexpr size_t lds = contract_split_lds<BlockOf<PROB, I, J>::B.ngroup>();
     static_assert(lds <= 160 * 1024, "split contraction exceeds the LDS of a CU");
-    return hipFuncSetAttribute((const void *)k_contract_split<PROB, I, J>,
+    return hipFuncSetAttribute((const void *)k_contract_split<PROB, I, J, I8>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess ? 0 : -1;
 }
 
-int prepare_split_kernels()
+template <bool I8>
+static int allow_all()
 {
-    int r = hipFuncSetAttribute((const void *)k_moments_split, hipFuncAttributeMaxDynamicSharedMemorySize,
+    int r = hipFuncSetAttribute((const void *)k_moments_split<I8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)MOMENTS_SPLIT_LDS) == hipSuccess ? 0 : -1;
-    r |= allow_lds<0, 0, 0>();
-    r |= allow_lds<1, 0, 0>();
-    r |= allow_lds<1, 0, 1>();
-    r |= allow_lds<1, 0, 2>();
-    r |= allow_lds<1, 1, 1>();
-    r |= allow_lds<1, 1, 2>();
-    r |= allow_lds<1, 2, 2>();
+    r |= allow_lds<0, 0, 0, I8>();
+    r |= allow_lds<1, 0, 0, I8>();
+    r |= allow_lds<1, 0, 1, I8>();
+    r |= allow_lds<1, 0, 2, I8>();
+    r |= allow_lds<1, 1, 1, I8>();
+    r |= allow_lds<1, 1, 2, I8>();
+    r |= allow_lds<1, 2, 2, I8>();
     return r;
 }
+
+int prepare_split_kernels() { return allow_all<false>() | allow_all<true>(); }
 
 }  // namespace p2s

@@ -1,6 +1,7 @@
-"""GPU tests of the split-FP32 form (moment and contraction products on the
-FP32 matrix cores on exact 10-bit operand slices, FP64 coupling, tables,
-intermediates and sums) against the CPU oracle and the FP64 GPU path.
+"""GPU tests of the split forms (moment and contraction products on the
+FP32 matrix cores on exact 10-bit operand slices, or on the INT8 matrix
+cores on exact 7-bit slices; FP64 coupling, tables, intermediates and
+sums) against the CPU oracle and the FP64 GPU path.
 
 Bar: relative Frobenius error <= 1e-8 per element, the precision target of
 the split form.  Every FP32 matrix-core sum is exact (integer slice
@@ -57,13 +58,17 @@ def rel(a, b, off):
                      np.linalg.norm(b[off[e]:off[e + 1]]) for e in range(len(off) - 1)])
 
 
+PRECISIONS = ("SPLIT_FP32", "SPLIT_INT8")
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
 @pytest.mark.parametrize("problem,N,Q", [(0, 4, (8, 8, 8)), (0, 6, (12, 10, 9)), (1, 3, (6, 6, 6)),
                                          (1, 5, (10, 9, 11)), (0, 8, (16, 16, 16)), (0, 2, (3, 4, 5))])
-def test_split_against_oracle(env, problem, N, Q):
+def test_split_against_oracle(env, problem, N, Q, prec):
     W, oracle, p2s = env["W"], env["oracle"], env["p2s"]
     w = small(W, problem, N, 3, Q, seed=100 + 10 * N + problem)
-    print("case problem %d N %d Q %s" % (problem, N, Q), flush=True)
-    out, off, st = fill(env, w, p2s.SPLIT_FP32)
+    print("case problem %d N %d Q %s %s" % (problem, N, Q, prec), flush=True)
+    out, off, st = fill(env, w, getattr(p2s, prec))
     ref, roff, rst = oracle.fill(w.problem, w.material, w.nodes, w.mat, w.orders, w.quad)
     assert np.array_equal(off, roff) and (st == 0).all()
     err = rel(out, ref, off)
@@ -77,7 +82,8 @@ def test_split_against_oracle(env, problem, N, Q):
         assert np.linalg.norm(M - M.T) <= BOUND * np.linalg.norm(M)
 
 
-def test_split_vector_n8_against_oracle(env):
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_split_vector_n8_against_oracle(env, prec):
     """The precision configuration: vector curl-curl + mass at N = 8 with
     16^3 points (1344 dofs), eight elements of the 8192-element workload
     (first, last and six between) against the oracle, and the same elements
@@ -86,21 +92,23 @@ def test_split_vector_n8_against_oracle(env):
     full = W.make("vector_n8")
     idx = np.array([0, 1, 1000, 2500, 4096, 6000, 8000, 8191])
     w = W.subset(full, idx)
-    out, off, st = fill(env, w, p2s.SPLIT_FP32)
+    out, off, st = fill(env, w, getattr(p2s, prec))
     out64, _, _ = fill(env, w, p2s.FP64)
     ref, roff, _ = oracle.fill(w.problem, w.material, w.nodes, w.mat, w.orders, w.quad)
     e_split, e_64 = rel(out, ref, off), rel(out64, ref, off)
-    print("vector N=8: split-FP32 max %.3e, FP64 max %.3e" % (e_split.max(), e_64.max()), flush=True)
+    print("vector N=8: %s max %.3e, FP64 max %.3e" % (prec, e_split.max(), e_64.max()), flush=True)
     assert (st == 0).all()
     assert e_64.max() <= 1e-10
     assert e_split.max() <= BOUND
 
 
-def test_split_moments_against_fp64(env):
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_split_moments_against_fp64(env, prec):
     W, p2s, torch = env["W"], env["p2s"], env["torch"]
     w = small(W, 1, 6, 4, (12, 12, 12), seed=7)
     nodes, mat = torch.from_numpy(w.nodes).cuda(), torch.from_numpy(w.mat).cuda()
-    m32 = env["ctx"].plan(w.problem, w.material, w.orders, w.quad, precision=p2s.SPLIT_FP32).moments(nodes, mat)
+    m32 = env["ctx"].plan(w.problem, w.material, w.orders, w.quad,
+                          precision=getattr(p2s, prec)).moments(nodes, mat)
     m64 = env["ctx"].plan(w.problem, w.material, w.orders, w.quad).moments(nodes, mat)
     a, b = m32.cpu().numpy(), m64.cpu().numpy()
     err = np.linalg.norm((a - b).reshape(w.E, -1), axis=1) / np.linalg.norm(b.reshape(w.E, -1), axis=1)
@@ -117,3 +125,5 @@ def test_split_argument_errors(env):
         ctx.plan(0, 0, [4], [[17, 8, 8]], precision=p2s.SPLIT_FP32)
     with pytest.raises(p2s.P2SError, match="split-FP32"):
         ctx.plan(0, 0, [4], [[8, 8, 8]], precision=p2s.SPLIT_FP32, method=p2s.METHOD_DIRECT)
+    with pytest.raises(p2s.P2SError, match="split-INT8"):
+        ctx.plan(0, 0, [4], [[17, 8, 8]], precision=p2s.SPLIT_INT8)
