@@ -156,11 +156,38 @@ __device__ __forceinline__ void stage_c_one(double (&acc)[N][N], const double (&
     }
 }
 
-template <int N, int X, int Y, int... Is>
-__device__ __forceinline__ void stage_c_all(double (&acc)[N][N], const double (&bv)[2 * N - 1],
-                                            cdouble *__restrict__ tb, std::integer_sequence<int, Is...>)
+// The coefficients of row p1 are loaded from a base that has passed
+// through an empty asm taking every result of row p1 - 2 as input: their
+// scalar loads cannot be issued before that row is done, so about two rows
+// of coefficients are live at a time.  Issued early, the ~90 coefficients
+// of a run (two scalar registers each) overflow the scalar register file
+// and are spilled into vector-register lanes, at two lane reads per FMA.
+template <int N>
+__device__ __forceinline__ cdouble *after_row(cdouble *tb, const double (&r)[N])
 {
-    (stage_c_one<N, X, Y, Is / N, Is % N>(acc, bv, tb), ...);
+    constexpr int A = 0, B = N > 1 ? 1 : 0, C = N > 2 ? 2 : 0, D = N > 3 ? 3 : 0, E = N > 4 ? 4 : 0,
+                  F = N > 5 ? 5 : 0, G = N > 6 ? 6 : 0, H = N > 7 ? 7 : 0;
+    asm volatile("" : "+s"(tb) : "v"(r[A]), "v"(r[B]), "v"(r[C]), "v"(r[D]), "v"(r[E]), "v"(r[F]), "v"(r[G]),
+                 "v"(r[H]));
+    return tb;
+}
+
+template <int N, int X, int Y, int P1, int... P2s>
+__device__ __forceinline__ void stage_c_row(double (&acc)[N][N], const double (&bv)[2 * N - 1],
+                                            cdouble *__restrict__ tb, std::integer_sequence<int, P2s...>)
+{
+    if constexpr (P1 >= 2)
+        tb = after_row<N>(tb, acc[P1 - 2]);
+    else
+        asm volatile("" : "+s"(tb) : "v"(bv[0]));
+    (stage_c_one<N, X, Y, P1, P2s>(acc, bv, tb), ...);
+}
+
+template <int N, int X, int Y, int... P1s>
+__device__ __forceinline__ void stage_c_all(double (&acc)[N][N], const double (&bv)[2 * N - 1],
+                                            cdouble *__restrict__ tb, std::integer_sequence<int, P1s...>)
+{
+    (stage_c_row<N, X, Y, P1s>(acc, bv, tb, std::make_integer_sequence<int, N>{}), ...);
 }
 
 template <int N, int T>
@@ -170,11 +197,8 @@ __device__ __forceinline__ void stage_c(double (&acc)[N][N], const double (&bv)[
     constexpr int X = T / 3, Y = T % 3;
     constexpr int off = kPackOffsets.off[N][T];
     static_assert(off == packed_offset(N, X, Y), "packed table layout");
-    cdouble *tb = (cdouble *)(pack + off);
-    // keep the table base opaque to loop-invariant motion so that every
-    // coefficient is a scalar load at an immediate offset
-    asm volatile("" : "+s"(tb));
-    stage_c_all<N, X, Y>(acc, bv, tb, std::make_integer_sequence<int, N * N>{});
+    // every coefficient is a scalar load at an immediate offset from the base
+    stage_c_all<N, X, Y>(acc, bv, (cdouble *)(pack + off), std::make_integer_sequence<int, N>{});
 }
 
 // Stage C of the sum-factorized direct quadrature: dense over the 2N Gauss
@@ -186,14 +210,15 @@ __device__ __forceinline__ void stage_c_points(double (&acc)[N][N], const double
 {
     constexpr int X = T / 3, Y = T % 3;
     cdouble *tb = (cdouble *)(pt + T * LIN_STRIDE_T);
-    asm volatile("" : "+s"(tb));
 #pragma unroll
-    for (int p1 = 0; p1 < fam_dim(X, N); ++p1)
+    for (int p1 = 0; p1 < fam_dim(X, N); ++p1) {
+        tb = after_row<N>(tb, acc[p1 >= 2 ? p1 - 2 : 0]);
 #pragma unroll
         for (int p2 = 0; p2 < fam_dim(Y, N); ++p2)
 #pragma unroll
             for (int q = 0; q < 2 * N; ++q)
                 acc[p1][p2] = fma(tb[p1 * LIN_STRIDE_M1 + p2 * KPAD + q], bv[q], acc[p1][p2]);
+    }
 }
 
 // Work-group id -> logical work item, so that consecutive items (the row
@@ -298,8 +323,13 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                                 double v[K];
 #pragma unroll
                                 for (int k = 0; k < K; ++k) v[k] = Ip[k * K * K];
-                                cdouble *Cu = (cdouble *)(lin + t.tu * LIN_STRIDE_T + M1 * LIN_STRIDE_M1);
-                                asm volatile("" : "+s"(Cu));
+                                // the base passes through an empty asm here, inside
+                                // the loop: the term's offset then folds into the
+                                // loads' immediates instead of one hoisted 64-bit
+                                // base per (m1, term) held in scalar registers
+                                const double *lp = lin;
+                                asm volatile("" : "+s"(lp));
+                                cdouble *Cu = (cdouble *)(lp + t.tu * LIN_STRIDE_T + M1 * LIN_STRIDE_M1);
                                 static_for<(J == I ? M1 : 0), NM_J>([&](auto mc) {
                                     constexpr int mm = decltype(mc)::value;
                                     constexpr uint32_t mk = DSF ? FULL : prod_mask(t.tu / 3, M1, t.tu % 3, mm);
