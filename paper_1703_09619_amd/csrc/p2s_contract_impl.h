@@ -509,10 +509,8 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
     if (__syncthreads_or(bad) && tid == 0) atomicOr(status + e, P2S_STATUS_NONFINITE_BIT);
 }
 
-// One launch per column block (I, J >= I): each kernel holds the code of a
-// single block, which keeps it within the instruction cache (a kernel with
-// all three column blocks of I = 0 missed in it two orders of magnitude more
-// often than one with a single block).
+// One launch per column block (I, J >= I), each kernel holding the code of
+// a single block: the scalar problem, and the vector problem above order 6.
 template <int PROB, int N, int I, int J, bool DSF = false, bool PACKED = false>
 __global__ __launch_bounds__((CS<PROB, N, I, J, J + 1, DSF>::THREADS), (N <= 6 ? 3 : 2)) void k_contract(
     const ElemDesc *__restrict__ desc, const int32_t *__restrict__ elist, int64_t e0, int64_t nitems,
@@ -542,12 +540,78 @@ static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_
                        elist, e0, nitems, padded, tab, mom, out, status, sK, sM);
 }
 
-// The blocks (I, J >= I) of one problem and order, one launch each.
+// All six blocks of the vector problem in one launch (orders up to 6), work
+// items in element order: the 33 items of an element (block by block, m1 by
+// m1) are consecutive, so after the remap below they run together on one
+// XCD.  The element matrix's rows are 4320 bytes at N = 6, so most 128-byte
+// lines of the output straddle two blocks or two items; written by
+// workgroups of one XCD at about the same time, their pieces merge in that
+// XCD's L2 before the line goes to HBM, while pieces written by separate
+// launches reach HBM as partial-line writes (a plain write of whole lines
+// runs about twice as fast as one that splits lines across launches).  Each
+// workgroup runs one block's body; the instruction footprint of six bodies
+// costs less than those partial writes.
+constexpr int kBlockI[6] = {0, 0, 0, 1, 1, 2};
+constexpr int kBlockJ[6] = {0, 1, 2, 1, 2, 2};
+
+template <int N, bool DSF>
+struct VectorBlocks {
+    template <int b>
+    using S = CS<1, N, kBlockI[b], kBlockJ[b], kBlockJ[b] + 1, DSF>;
+    static constexpr int THREADS = cmax(cmax(cmax(S<0>::THREADS, S<1>::THREADS), cmax(S<2>::THREADS, S<3>::THREADS)),
+                                        cmax(S<4>::THREADS, S<5>::THREADS));
+    static constexpr int BUF =
+        cmax(cmax(cmax(S<0>::BUF, S<1>::BUF), cmax(S<2>::BUF, S<3>::BUF)), cmax(S<4>::BUF, S<5>::BUF));
+    // first item of block b within an element, and items per element
+    static constexpr int first(int b)
+    {
+        int o = 0;
+        for (int x = 0; x < b; ++x) o += comp_dim(1, N, kBlockI[x], 0);
+        return o;
+    }
+    static constexpr int ITEMS = first(6);
+};
+
+template <int N, bool DSF = false, bool PACKED = false>
+__global__ __launch_bounds__((VectorBlocks<N, DSF>::THREADS), 3) void k_contract_vector(
+    const ElemDesc *__restrict__ desc, const int32_t *__restrict__ elist, int64_t e0, int64_t nitems,
+    int64_t padded, const double *__restrict__ tab, const double *__restrict__ mom,
+    double *__restrict__ out, uint32_t *__restrict__ status, double sK, double sM)
+{
+    using V = VectorBlocks<N, DSF>;
+    const int64_t item = xcd_remap(blockIdx.x, padded);
+    if (item >= nitems) return;
+    const int64_t eidx = e0 + item / V::ITEMS;
+    const int r = (int)(item % V::ITEMS);
+    const int64_t e = elist ? (int64_t)elist[eidx] : eidx;
+    const ElemDesc d = desc[e];
+    __shared__ __attribute__((aligned(16))) double smem[V::BUF];
+    static_for<0, 6>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        constexpr int I = kBlockI[b], J = kBlockJ[b];
+        constexpr int lo = V::first(b), n = comp_dim(1, N, I, 0);
+        if (r >= lo && r < lo + n)
+            contract_item<1, N, I, J, J + 1, DSF, PACKED>(d, e, r - lo, tab, mom, out, status, sK, sM, smem,
+                                                          V::THREADS);
+    });
+}
+
+// The blocks (I, J >= I) of one problem and order: the scalar problem's
+// single block, the vector problem's six in one launch up to order 6 and
+// one launch each above (from order 7 on a CU holds a single workgroup).
 template <int PROB, int N, bool DSF = false, bool PACKED = false>
 static void launch_contract_t(const ElemDesc *desc, const int32_t *elist, int64_t e0, int64_t count,
                               const double *tab, const double *mom, double *out, uint32_t *status,
                               double sK, double sM, hipStream_t st)
 {
+    if constexpr (PROB == 1 && N <= 6) {
+        using V = VectorBlocks<N, DSF>;
+        const int64_t nitems = count * V::ITEMS;
+        const int64_t padded = (nitems + 7) / 8 * 8;
+        hipLaunchKernelGGL((k_contract_vector<N, DSF, PACKED>), dim3((unsigned)padded), dim3(V::THREADS), 0, st,
+                           desc, elist, e0, nitems, padded, tab, mom, out, status, sK, sM);
+        return;
+    }
     launch_contract_i<PROB, N, 0, 0, DSF, PACKED>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
     if constexpr (PROB == 1) {
         launch_contract_i<PROB, N, 0, 1, DSF, PACKED>(desc, elist, e0, count, tab, mom, out, status, sK, sM, st);
