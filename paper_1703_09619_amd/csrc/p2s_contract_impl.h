@@ -543,14 +543,14 @@ static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_
 // All six blocks of the vector problem in one launch (orders up to 6), work
 // items in element order: the 33 items of an element (block by block, m1 by
 // m1) are consecutive, so after the remap below they run together on one
-// XCD.  The element matrix's rows are 4320 bytes at N = 6, so most 128-byte
-// lines of the output straddle two blocks or two items; written by
-// workgroups of one XCD at about the same time, their pieces merge in that
-// XCD's L2 before the line goes to HBM, while pieces written by separate
-// launches reach HBM as partial-line writes (a plain write of whole lines
-// runs about twice as fast as one that splits lines across launches).  Each
-// workgroup runs one block's body; the instruction footprint of six bodies
-// costs less than those partial writes.
+// XCD.  The element matrix's rows are 4320 bytes at N = 6 and the mirrored
+// row segments 288 bytes, so about a quarter of the 128-byte lines of the
+// output are written in pieces by two work items, and a fourteenth by two
+// blocks.  Written by workgroups of one XCD at about the same time, the
+// pieces merge in that XCD's L2 before the line goes to HBM; written by
+// separate launches, they reach HBM as partial-line writes, at about half
+// the rate of whole lines.  Each workgroup runs one block's body; the
+// instruction footprint of six bodies costs less than those partial writes.
 constexpr int kBlockI[6] = {0, 0, 0, 1, 1, 2};
 constexpr int kBlockJ[6] = {0, 1, 2, 1, 2, 2};
 
