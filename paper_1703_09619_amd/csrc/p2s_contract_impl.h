@@ -84,8 +84,10 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
 // Compile-time shape of the work item of row component I against the column
-// components JB <= J < JE: lane count, LDS batching and store tile.
-template <int PROB, int N, int I, int JB = I, int JE = num_comp(PROB), bool DSF = false>
+// components JB <= J < JE: lane count, LDS batching and store tile.  PAIR
+// (diagonal block only): the item holds the two row bands m1 and NM - 1 - m1,
+// whose triangles m2 >= m1 together span NM + 1 column slabs.
+template <int PROB, int N, int I, int JB = I, int JE = num_comp(PROB), bool DSF = false, bool PAIR = false>
 struct CS {
     // contracted extent per axis: the 2N-1 Legendre degrees of the moments,
     // or (sum-factorized direct quadrature) the 2N Gauss points
@@ -101,7 +103,8 @@ struct CS {
         int m = 0;
         for (int j = JB; j < JE; ++j) {
             int v = 0;
-            if (what == 0) v = comp_dim(PROB, N, j, 0) * NN_I * comp_dim(PROB, N, j, 1);  // lane tasks
+            if (what == 0)  // lane tasks
+                v = (comp_dim(PROB, N, j, 0) + (PAIR ? 1 : 0)) * NN_I * comp_dim(PROB, N, j, 1);
             if (what == 1) v = make_block_c(PROB, I, j).ngroup;
             if (what == 2) v = comp_dim(PROB, N, j, 1);
             if (what == 3) v = comp_dim(PROB, N, j, 0) * comp_dim(PROB, N, j, 1) * comp_dim(PROB, N, j, 2);
@@ -116,13 +119,17 @@ struct CS {
     static constexpr int THREADS =
         N <= 6 ? ((max_over_j(0) + 63) / 64) * 64 : ((max_over_j(0) + 255) / 256) * 256;
     static constexpr int MAXG = max_over_j(1);
-    static constexpr int A_DOUBLES = N * K * KS;                    // stage-A result per group
+    static constexpr int A_ROWS = PAIR ? NM_I + 1 : N;              // column slabs held in LDS
+    static constexpr int A_DOUBLES = A_ROWS * K * KS;               // stage-A result per group
     static constexpr int C_DOUBLES = NN_I * max_over_j(2) * KS;      // stage-B coefficients per group
     static constexpr int GROUP_DOUBLES = A_DOUBLES + C_DOUBLES;
     // groups per LDS batch: at most 40 KiB up to N = 6, so that four
     // three-wave workgroups share a CU (the 168-VGPR bound of k_contract
-    // allows twelve waves per CU), ~62 KiB above
-    static constexpr int G = cmax(1, cmin(MAXG, (N <= 6 ? 5120 : 7936) / GROUP_DOUBLES));
+    // allows twelve waves per CU), ~62 KiB above; paired items run in the
+    // four-wave workgroups of the single-launch vector kernel, three to a
+    // CU, and take up to 52 KiB
+    static constexpr int G =
+        cmax(1, cmin(MAXG, (N <= 6 ? (PAIR ? 6656 : 5120) : 7936) / GROUP_DOUBLES));
     static constexpr int TILE_MIN = NN_I * NP_I * (max_over_j(4) + 2);  // one m2 of the store tile
     static constexpr int BUF = cmax(G * GROUP_DOUBLES, TILE_MIN);
     static constexpr int SA = ((K * K + 63) / 64) * 64;              // stage-A workers per group
@@ -141,6 +148,20 @@ __device__ __forceinline__ void store_out2(double *p, double a, double b)
     __builtin_nontemporal_store(v, reinterpret_cast<nt_double2 *>(p));
 }
 __device__ __forceinline__ void store_out(double *p, double a) { __builtin_nontemporal_store(a, p); }
+// Two values of a mirrored row segment [lo, hi).  The segments are short
+// (NR values) and their ends fall inside 128-byte lines that the neighbouring
+// bands' segments complete; a line wholly inside the segment is streamed like
+// the rest of the output, while a shared line takes an ordinary store, which
+// the L2 holds until the other piece arrives and then writes back whole.
+// Streamed, the pieces reach HBM as partial-line writes.
+__device__ __forceinline__ void store_mirror2(double *p, double a, double b, const double *lo, const double *hi)
+{
+    const uintptr_t line = reinterpret_cast<uintptr_t>(p) & ~uintptr_t(127);
+    if (line >= reinterpret_cast<uintptr_t>(lo) && line + 128 <= reinterpret_cast<uintptr_t>(hi))
+        store_out2(p, a, b);
+    else
+        *reinterpret_cast<double2 *>(p) = make_double2(a, b);
+}
 
 template <int N, int X, int Y, int P1, int P2>
 __device__ __forceinline__ void stage_c_one(double (&acc)[N][N], const double (&bv)[2 * N - 1],
@@ -238,22 +259,34 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t total_padded)
 // the moments are replaced by the coupling samples at the 2N-point rule
 // (mom = the sample buffer) and the linearization coefficients by the
 // weighted basis products w_a X_m1(x_a) Y_m2(x_a) at those points (dense).
-template <int PROB, int N, int I, int JB = I, int JE = num_comp(PROB), bool DSF = false, bool PACKED = false>
+// PAIR (diagonal block, JB = I, JE = I + 1): m1 is a pair index p and the
+// item holds row bands p and NM - 1 - p (one band when they coincide); the
+// lanes of the first band come first, and the stage-A rows of the two bands'
+// triangles m2 >= m1 lie one after the other in LDS.  MERGE: the lines that
+// a mirrored segment shares with its neighbours take ordinary stores (see
+// store_mirror2); it pays only where the items that write the other pieces
+// run alongside (the single-launch vector kernel with paired items).
+template <int PROB, int N, int I, int JB = I, int JE = num_comp(PROB), bool DSF = false, bool PACKED = false,
+          bool PAIR = false, bool MERGE = false>
 __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int m1,
                                               const double *__restrict__ tab, const double *__restrict__ mom,
                                               double *__restrict__ out, uint32_t *__restrict__ status,
                                               double sK, double sM, double *__restrict__ smem, int nthreads)
 {
-    using S = CS<PROB, N, I, JB, JE, DSF>;
+    using S = CS<PROB, N, I, JB, JE, DSF, PAIR>;
+    static_assert(!PAIR || (JB == I && JE == I + 1), "paired items belong to a diagonal block");
     constexpr int K = S::K, KS = S::KS, NC = S::NC, NDOF = S::NDOF, G = S::G;
-    constexpr int NN_I = S::NN_I, NP_I = S::NP_I;
+    constexpr int NM_I = S::NM_I, NN_I = S::NN_I, NP_I = S::NP_I, A_ROWS = S::A_ROWS;
     constexpr uint32_t FULL = (1u << K) - 1u;
     const double *lin = DSF ? tab + TAB_PT + N * PT_STRIDE_N : tab + TAB_LIN;
     const double *pack = tab + TAB_PACK;
     const double *I0 = mom + (DSF ? d.alpha_off : d.mom_off);
     double *obase = out + d.out_off;
     const int tid = threadIdx.x;
-    const int rowbase = comp_offset(PROB, N, I) + m1 * NN_I * NP_I;
+    // row bands: m1a = m1, and with PAIR the mirror band m1b when distinct
+    const int m1a = m1;
+    const int m1b = PAIR ? NM_I - 1 - m1 : m1;
+    const bool two = PAIR && m1b > m1a;
     bool bad = false;
 
     static_for<JB, JE>([&](auto Jc) {
@@ -263,13 +296,20 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                       NP_J = comp_dim(PROB, N, J, 2);
         constexpr int NBATCH = (BK.ngroup + G - 1) / G;
         // symmetric: inside the diagonal block only m2 >= m1
-        const int m2lo = (J == I) ? m1 : 0;
-        const int nm = NM_J - m2lo;
-        const int T = nm * NN_I * NN_J;
-        const bool active = tid < T;
-        const int n2 = tid % NN_J;
-        const int m2 = m2lo + (tid / NN_J) % nm;
-        const int n1 = tid / (NN_J * nm);
+        const int nma = NM_J - ((J == I) ? m1a : 0);
+        const int Ta = nma * NN_I * NN_J;
+        const int nmb = two ? NM_J - m1b : 0;
+        const bool bandb = tid >= Ta;   // lane of the second band
+        const int lt = bandb ? tid - Ta : tid;
+        const int m2lo = (J == I) ? (bandb ? m1b : m1a) : 0;
+        const int nm = bandb ? nmb : nma;
+        const bool active = bandb ? lt < nmb * NN_I * NN_J : true;
+        const int n2 = lt % NN_J;
+        const int m2 = active ? m2lo + (lt / NN_J) % nm : m2lo;
+        const int n1 = active ? lt / (NN_J * nm) : 0;
+        // stage-A row of this lane's m2: the absolute m2, or with PAIR the
+        // compact rows of the first band's triangle, then the second's
+        const int arow_m = PAIR ? (bandb ? nma + (m2 - m1b) : m2 - m1a) : m2;
         double acc[N][N];
 #pragma unroll
         for (int a = 0; a < N; ++a)
@@ -303,9 +343,9 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                 const int gl = w / S::SA;
                 const int lq = w - gl * S::SA;
                 if (lq < K * K) {
-                    double a[N];
+                    double a[A_ROWS];
 #pragma unroll
-                    for (int mm = 0; mm < N; ++mm) a[mm] = 0.0;
+                    for (int r = 0; r < A_ROWS; ++r) a[r] = 0.0;
                     static_for<0, ng>([&](auto gc) {
                         constexpr int g = decltype(gc)::value;
                         if (gl != g) return;
@@ -313,9 +353,12 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                         // constant, so the degree masks of the k-sum and the
                         // coefficient offsets are constants and every
                         // coefficient is a scalar load
-                        static_for<0, S::NM_I>([&](auto Mc) {
+                        static_for<0, PAIR ? (NM_I + 1) / 2 : NM_I>([&](auto Mc) {
                             constexpr int M1 = decltype(Mc)::value;
                             if (m1 != M1) return;
+                            // PAIR: the second band and its first row
+                            constexpr int M1B = PAIR ? NM_I - 1 - M1 : M1;
+                            constexpr int RB = NM_J - M1;
                             static_for<BK.gstart[g0 + g], BK.gstart[g0 + g + 1]>([&](auto sc_) {
                                 constexpr TermC t = BK.t[decltype(sc_)::value];
                                 const double sc = (t.scale ? sM : sK) * (double)t.sign;
@@ -337,16 +380,39 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
 #pragma unroll
                                     for (int k = 0; k < K; ++k)
                                         if ((mk >> k) & 1u) xs = fma(Cu[mm * KPAD + k], v[k], xs);
-                                    a[mm] = fma(sc, xs, a[mm]);
+                                    constexpr int r = PAIR ? mm - M1 : mm;
+                                    a[r] = fma(sc, xs, a[r]);
                                 });
+                                if constexpr (PAIR && M1B > M1) {
+                                    // the second band reuses the moment column v
+                                    cdouble *Cb = (cdouble *)(lp + t.tu * LIN_STRIDE_T + M1B * LIN_STRIDE_M1);
+                                    static_for<M1B, NM_J>([&](auto mc) {
+                                        constexpr int mm = decltype(mc)::value;
+                                        constexpr uint32_t mk = DSF ? FULL : prod_mask(t.tu / 3, M1B, t.tu % 3, mm);
+                                        double xs = 0.0;
+#pragma unroll
+                                        for (int k = 0; k < K; ++k)
+                                            if ((mk >> k) & 1u) xs = fma(Cb[mm * KPAD + k], v[k], xs);
+                                        constexpr int r = RB + mm - M1B;
+                                        a[r] = fma(sc, xs, a[r]);
+                                    });
+                                }
                             });
                         });
                     });
                     const int l = lq / K, q = lq - (lq / K) * K;
                     double *Ab = Abuf + gl * S::A_DOUBLES + l * KS + q;
+                    if constexpr (PAIR) {
+                        const int nrow = nma + nmb;
 #pragma unroll
-                    for (int mm = 0; mm < NM_J; ++mm)
-                        if (mm >= m2lo) Ab[mm * K * KS] = a[mm];
+                        for (int r = 0; r < A_ROWS; ++r)
+                            if (r < nrow) Ab[r * K * KS] = a[r];
+                    } else {
+                        const int mlo = (J == I) ? m1a : 0;
+#pragma unroll
+                        for (int mm = 0; mm < NM_J; ++mm)
+                            if (mm >= mlo) Ab[mm * K * KS] = a[mm];
+                    }
                 }
             }
             __syncthreads();
@@ -358,7 +424,7 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                     // stage B: two set bits of the degree mask per step
                     uint32_t ml = DSF ? FULL : c_cmasks.m[tv][n1][n2];
                     const double *crow = Cbuf + g * (NN_I * NN_J * KS) + (n1 * NN_J + n2) * KS;
-                    const double *arow = Abuf + g * S::A_DOUBLES + m2 * K * KS;
+                    const double *arow = Abuf + g * S::A_DOUBLES + arow_m * K * KS;
                     while (ml) {
                         const int l0 = __ffs(ml) - 1;
                         ml &= ml - 1u;
@@ -390,21 +456,25 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
         });
 
         // coalesced stores through LDS: the tile holds all rows (n1, p1) of
-        // the item and the columns (m2, n2, p2) of a chunk of m2 >= m2lo, so
-        // that every mirrored row segment (the item's NR values) is written
-        // whole by one workgroup in one pass
-        {
+        // a row band and the columns (m2, n2, p2) of a chunk of the band's
+        // m2, so that every mirrored row segment (the band's NR values) is
+        // written whole by one workgroup in one pass; one band after the other
+        for (int band = 0; band < (two ? 2 : 1); ++band) {
+            const int m1s = band ? m1b : m1a;
+            const int mlo = (J == I) ? m1s : 0;  // first column slab of the band
+            const int rowbase = comp_offset(PROB, N, I) + m1s * NN_I * NP_I;
+            const bool mine = active && bandb == (band != 0);
             constexpr int NR = NN_I * NP_I;      // tile rows
             constexpr int CW = NN_J * NP_J;      // tile columns per m2
             constexpr int CM = cmax(1, (S::BUF / NR - 1) / CW);  // m2 per chunk
             static_assert(NR * ((CM * CW) | 1) <= S::BUF, "store tile exceeds the LDS buffer");
-            for (int ma = m2lo; ma < NM_J; ma += CM) {
+            for (int ma = mlo; ma < NM_J; ma += CM) {
                 const int mb = ma + CM < NM_J ? ma + CM : NM_J;
                 const int W = (mb - ma) * CW;    // tile width
                 // odd row stride: the transposed (mirror) reads below step two
                 // rows per lane, which an odd stride spreads over distinct banks
                 const int WS = W | 1;
-                if (active && m2 >= ma && m2 < mb) {
+                if (mine && m2 >= ma && m2 < mb) {
                     double *tl = smem + n1 * NP_I * WS + ((m2 - ma) * NN_J + n2) * NP_J;
 #pragma unroll
                     for (int p1 = 0; p1 < NP_I; ++p1)
@@ -435,7 +505,7 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                     continue;
                 }
                 // mirrored rows start after the diagonal slab m2 == m1 of block (I,I)
-                const int cmir = (J == I && ma == m2lo) ? CW : 0;
+                const int cmir = (J == I && ma == mlo) ? CW : 0;
                 double *drow = obase + (int64_t)rowbase * NDOF + colj;
                 const bool d16 = (NDOF % 2 == 0) && (W % 2 == 0) &&
                                  ((reinterpret_cast<uintptr_t>(drow) & 15u) == 0);
@@ -480,7 +550,11 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
                     int q = tid / hr, h = tid - q * hr;  // tile column cmir + q, row pair h
                     while (q < nc) {
                         const int c = cmir + q, r = 2 * h;
-                        store_out2(mrow + (int64_t)c * NDOF + r, smem[r * WS + c], smem[(r + 1) * WS + c]);
+                        double *seg = mrow + (int64_t)c * NDOF;
+                        if constexpr (MERGE)
+                            store_mirror2(seg + r, smem[r * WS + c], smem[(r + 1) * WS + c], seg, seg + NR);
+                        else
+                            store_out2(seg + r, smem[r * WS + c], smem[(r + 1) * WS + c]);
                         q += dq;
                         h += dh;
                         if (h >= hr) {
@@ -541,9 +615,9 @@ static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_
 }
 
 // All six blocks of the vector problem in one launch (orders up to 6), work
-// items in element order: the 33 items of an element (block by block, m1 by
-// m1) are consecutive, so after the remap below they run together on one
-// XCD.  The element matrix's rows are 4320 bytes at N = 6 and the mirrored
+// items in element order: the items of an element (block by block, m1 by
+// m1; 25 at N = 6) are consecutive, so after the remap below they run
+// together on one XCD.  The element matrix's rows are 4320 bytes at N = 6 and the mirrored
 // row segments 288 bytes, so about a quarter of the 128-byte lines of the
 // output are written in pieces by two work items, and a fourteenth by two
 // blocks.  Written by workgroups of one XCD at about the same time, the
@@ -554,19 +628,32 @@ static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_
 constexpr int kBlockI[6] = {0, 0, 0, 1, 1, 2};
 constexpr int kBlockJ[6] = {0, 1, 2, 1, 2, 2};
 
+// The diagonal blocks' items are paired (row bands m1 and NM - 1 - m1): an
+// unpaired item of a diagonal block fills only the lanes of its triangle
+// m2 >= m1, on average half of them, and its length varies with m1; a pair
+// spans NM + 1 slabs whatever m1, close to an off-diagonal item's NM, and its
+// two bands share the moment loads of stage A.  Items of about equal length
+// finish, and store, at about the same time, which is what lets the L2 merge
+// the pieces of the lines they share (MERGE).
 template <int N, bool DSF>
 struct VectorBlocks {
     template <int b>
-    using S = CS<1, N, kBlockI[b], kBlockJ[b], kBlockJ[b] + 1, DSF>;
+    using S = CS<1, N, kBlockI[b], kBlockJ[b], kBlockJ[b] + 1, DSF, kBlockI[b] == kBlockJ[b]>;
     static constexpr int THREADS = cmax(cmax(cmax(S<0>::THREADS, S<1>::THREADS), cmax(S<2>::THREADS, S<3>::THREADS)),
                                         cmax(S<4>::THREADS, S<5>::THREADS));
     static constexpr int BUF =
         cmax(cmax(cmax(S<0>::BUF, S<1>::BUF), cmax(S<2>::BUF, S<3>::BUF)), cmax(S<4>::BUF, S<5>::BUF));
-    // first item of block b within an element, and items per element
+    // items of block b, first item of block b within an element, and items
+    // per element
+    static constexpr int items(int b)
+    {
+        const int nm = comp_dim(1, N, kBlockI[b], 0);
+        return kBlockI[b] == kBlockJ[b] ? (nm + 1) / 2 : nm;
+    }
     static constexpr int first(int b)
     {
         int o = 0;
-        for (int x = 0; x < b; ++x) o += comp_dim(1, N, kBlockI[x], 0);
+        for (int x = 0; x < b; ++x) o += items(x);
         return o;
     }
     static constexpr int ITEMS = first(6);
@@ -589,10 +676,10 @@ __global__ __launch_bounds__((VectorBlocks<N, DSF>::THREADS), 3) void k_contract
     static_for<0, 6>([&](auto bc) {
         constexpr int b = decltype(bc)::value;
         constexpr int I = kBlockI[b], J = kBlockJ[b];
-        constexpr int lo = V::first(b), n = comp_dim(1, N, I, 0);
+        constexpr int lo = V::first(b), n = V::items(b);
         if (r >= lo && r < lo + n)
-            contract_item<1, N, I, J, J + 1, DSF, PACKED>(d, e, r - lo, tab, mom, out, status, sK, sM, smem,
-                                                          V::THREADS);
+            contract_item<1, N, I, J, J + 1, DSF, PACKED, I == J, true>(d, e, r - lo, tab, mom, out, status, sK,
+                                                                        sM, smem, V::THREADS);
     });
 }
 
