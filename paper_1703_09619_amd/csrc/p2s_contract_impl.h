@@ -125,11 +125,12 @@ struct CS {
     static constexpr int GROUP_DOUBLES = A_DOUBLES + C_DOUBLES;
     // groups per LDS batch: at most 40 KiB up to N = 6, so that four
     // three-wave workgroups share a CU (the 168-VGPR bound of k_contract
-    // allows twelve waves per CU), ~62 KiB above; paired items run in the
-    // four-wave workgroups of the single-launch vector kernel, three to a
-    // CU, and take up to 52 KiB
+    // allows twelve waves per CU), ~62 KiB above; paired items, whose groups
+    // are larger, at most 32 KiB: three groups per batch at N = 6, which
+    // measured faster than four (the unrolled groups of a batch hold fewer
+    // coefficients in scalar registers at once, so fewer spill)
     static constexpr int G =
-        cmax(1, cmin(MAXG, (N <= 6 ? (PAIR ? 6656 : 5120) : 7936) / GROUP_DOUBLES));
+        cmax(1, cmin(MAXG, (N <= 6 ? (PAIR ? 4096 : 5120) : 7936) / GROUP_DOUBLES));
     static constexpr int TILE_MIN = NN_I * NP_I * (max_over_j(4) + 2);  // one m2 of the store tile
     static constexpr int BUF = cmax(G * GROUP_DOUBLES, TILE_MIN);
     static constexpr int SA = ((K * K + 63) / 64) * 64;              // stage-A workers per group
