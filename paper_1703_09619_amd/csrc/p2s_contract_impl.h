@@ -128,9 +128,12 @@ struct CS {
     // allows twelve waves per CU), ~62 KiB above; paired items, whose groups
     // are larger, at most 32 KiB: three groups per batch at N = 6, which
     // measured faster than four (the unrolled groups of a batch hold fewer
-    // coefficients in scalar registers at once, so fewer spill)
+    // coefficients in scalar registers at once, so fewer spill).  The
+    // point-table form (DSF) keeps four (52 KiB): two per batch, what 32 KiB
+    // leaves of its larger groups, measured slower
+    static constexpr int PAIR_BUDGET = DSF ? 6656 : 4096;
     static constexpr int G =
-        cmax(1, cmin(MAXG, (N <= 6 ? (PAIR ? 4096 : 5120) : 7936) / GROUP_DOUBLES));
+        cmax(1, cmin(MAXG, (N <= 6 ? (PAIR ? PAIR_BUDGET : 5120) : 7936) / GROUP_DOUBLES));
     static constexpr int TILE_MIN = NN_I * NP_I * (max_over_j(4) + 2);  // one m2 of the store tile
     static constexpr int BUF = cmax(G * GROUP_DOUBLES, TILE_MIN);
     static constexpr int SA = ((K * K + 63) / 64) * 64;              // stage-A workers per group
