@@ -269,9 +269,10 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t total_padded)
 // triangles m2 >= m1 lie one after the other in LDS.  MERGE: the lines that
 // a mirrored segment shares with its neighbours take ordinary stores (see
 // store_mirror2); it pays only where the items that write the other pieces
-// run alongside (the single-launch vector kernel with paired items).
+// run alongside (the single-launch vector kernel with paired items).  SMEM:
+// doubles of smem available to the store tile (0: the item's own BUF).
 template <int PROB, int N, int I, int JB = I, int JE = num_comp(PROB), bool DSF = false, bool PACKED = false,
-          bool PAIR = false, bool MERGE = false>
+          bool PAIR = false, bool MERGE = false, int SMEM = 0>
 __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int m1,
                                               const double *__restrict__ tab, const double *__restrict__ mom,
                                               double *__restrict__ out, uint32_t *__restrict__ status,
@@ -470,8 +471,9 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
             const bool mine = active && bandb == (band != 0);
             constexpr int NR = NN_I * NP_I;      // tile rows
             constexpr int CW = NN_J * NP_J;      // tile columns per m2
-            constexpr int CM = cmax(1, (S::BUF / NR - 1) / CW);  // m2 per chunk
-            static_assert(NR * ((CM * CW) | 1) <= S::BUF, "store tile exceeds the LDS buffer");
+            constexpr int TB = SMEM > 0 ? SMEM : S::BUF;
+            constexpr int CM = cmax(1, (TB / NR - 1) / CW);  // m2 per chunk
+            static_assert(NR * ((CM * CW) | 1) <= TB, "store tile exceeds the LDS buffer");
             for (int ma = mlo; ma < NM_J; ma += CM) {
                 const int mb = ma + CM < NM_J ? ma + CM : NM_J;
                 const int W = (mb - ma) * CW;    // tile width
@@ -645,8 +647,16 @@ struct VectorBlocks {
     using S = CS<1, N, kBlockI[b], kBlockJ[b], kBlockJ[b] + 1, DSF, kBlockI[b] == kBlockJ[b]>;
     static constexpr int THREADS = cmax(cmax(cmax(S<0>::THREADS, S<1>::THREADS), cmax(S<2>::THREADS, S<3>::THREADS)),
                                         cmax(S<4>::THREADS, S<5>::THREADS));
-    static constexpr int BUF =
-        cmax(cmax(cmax(S<0>::BUF, S<1>::BUF), cmax(S<2>::BUF, S<3>::BUF)), cmax(S<4>::BUF, S<5>::BUF));
+    // at N = 6 the store tile takes all the LDS a workgroup gets when the CU
+    // holds twelve waves (three per SIMD, what the registers allow): fewer,
+    // longer chunks per row, so fewer row segments split between chunks
+    // (52 KiB against the batches' 38 KiB measured 3 % faster).  Lower
+    // orders need fewer registers and may hold more waves, which a larger
+    // tile would cap.
+    static constexpr int WGS_PER_CU = cmax(1, 12 / (THREADS / 64));
+    static constexpr int LDS_FIT = N == 6 ? (160 * 1024 / WGS_PER_CU - 1024) / 8 : 0;
+    static constexpr int BUF = cmax(
+        LDS_FIT, cmax(cmax(cmax(S<0>::BUF, S<1>::BUF), cmax(S<2>::BUF, S<3>::BUF)), cmax(S<4>::BUF, S<5>::BUF)));
     // items of block b, first item of block b within an element, and items
     // per element
     static constexpr int items(int b)
@@ -682,8 +692,8 @@ __global__ __launch_bounds__((VectorBlocks<N, DSF>::THREADS), 3) void k_contract
         constexpr int I = kBlockI[b], J = kBlockJ[b];
         constexpr int lo = V::first(b), n = V::items(b);
         if (r >= lo && r < lo + n)
-            contract_item<1, N, I, J, J + 1, DSF, PACKED, I == J, true>(d, e, r - lo, tab, mom, out, status, sK,
-                                                                        sM, smem, V::THREADS);
+            contract_item<1, N, I, J, J + 1, DSF, PACKED, I == J, true, V::BUF>(d, e, r - lo, tab, mom, out,
+                                                                                status, sK, sM, smem, V::THREADS);
     });
 }
 
