@@ -650,11 +650,15 @@ struct VectorBlocks {
     // at N = 6 the store tile takes all the LDS a workgroup gets when the CU
     // holds twelve waves (three per SIMD, what the registers allow): fewer,
     // longer chunks per row, so fewer row segments split between chunks
-    // (52 KiB against the batches' 38 KiB measured 3 % faster).  Lower
-    // orders need fewer registers and may hold more waves, which a larger
-    // tile would cap.
+    // (52 KiB against the batches' 38 KiB measured 3 % faster).  The share
+    // is rounded down to a multiple of 2560 bytes, less 512 bytes for the
+    // kernel's other shared variables: at N = 6 a workgroup of 53,504 bytes
+    // ran three to a CU, one of 53,840 bytes (a third of 160 KiB less 1 KiB)
+    // measured 20 % slower, as with two, which fits LDS allocated in blocks
+    // of 1280 or 2560 bytes.  Lower orders need fewer registers and may hold
+    // more waves, which a larger tile would cap.
     static constexpr int WGS_PER_CU = cmax(1, 12 / (THREADS / 64));
-    static constexpr int LDS_FIT = N == 6 ? (160 * 1024 / WGS_PER_CU - 1024) / 8 : 0;
+    static constexpr int LDS_FIT = N == 6 ? ((160 * 1024 / WGS_PER_CU) / 2560 * 2560 - 512) / 8 : 0;
     static constexpr int BUF = cmax(
         LDS_FIT, cmax(cmax(cmax(S<0>::BUF, S<1>::BUF), cmax(S<2>::BUF, S<3>::BUF)), cmax(S<4>::BUF, S<5>::BUF)));
     // items of block b, first item of block b within an element, and items
