@@ -591,21 +591,36 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
 
 // One launch per column block (I, J >= I), each kernel holding the code of
 // a single block: the scalar problem, and the vector problem above order 6.
+// The scalar problem's block is diagonal: up to order 6 its items are
+// paired like those of the single-launch vector kernel (a whole pair fills
+// NM + 1 slabs' worth of lanes where an unpaired item fills on average half
+// of its workgroup; the scalar N = 6 contraction measured 23 % faster).
+// Orders 7 and 8 stay unpaired: at order 8 a pair needs 576 lanes, more
+// than the 512 of the unpaired workgroup, and order 7 was not measured.
+template <int PROB, int N, int I, int J, bool DSF>
+struct BlockItems {
+    static constexpr bool PAIR = PROB == 0 && N <= 6;
+    using S = CS<PROB, N, I, J, J + 1, DSF, PAIR>;
+    static constexpr int ITEMS = PAIR ? (S::NM_I + 1) / 2 : S::NM_I;
+};
+
 template <int PROB, int N, int I, int J, bool DSF = false, bool PACKED = false>
-__global__ __launch_bounds__((CS<PROB, N, I, J, J + 1, DSF>::THREADS), (N <= 6 ? 3 : 2)) void k_contract(
+__global__ __launch_bounds__((BlockItems<PROB, N, I, J, DSF>::S::THREADS), (N <= 6 ? 3 : 2)) void k_contract(
     const ElemDesc *__restrict__ desc, const int32_t *__restrict__ elist, int64_t e0, int64_t nitems,
     int64_t padded, const double *__restrict__ tab, const double *__restrict__ mom,
     double *__restrict__ out, uint32_t *__restrict__ status, double sK, double sM)
 {
-    using S = CS<PROB, N, I, J, J + 1, DSF>;
+    using B = BlockItems<PROB, N, I, J, DSF>;
+    using S = typename B::S;
     const int64_t item = xcd_remap(blockIdx.x, padded);
     if (item >= nitems) return;
-    const int64_t eidx = e0 + item / S::NM_I;
+    const int64_t eidx = e0 + item / B::ITEMS;
     const int64_t e = elist ? (int64_t)elist[eidx] : eidx;
-    const int m1 = (int)(item % S::NM_I);
+    const int m1 = (int)(item % B::ITEMS);
     const ElemDesc d = desc[e];
     __shared__ __attribute__((aligned(16))) double smem[S::BUF];
-    contract_item<PROB, N, I, J, J + 1, DSF, PACKED>(d, e, m1, tab, mom, out, status, sK, sM, smem, S::THREADS);
+    contract_item<PROB, N, I, J, J + 1, DSF, PACKED, B::PAIR>(d, e, m1, tab, mom, out, status, sK, sM, smem,
+                                                              S::THREADS);
 }
 
 template <int PROB, int N, int I, int J, bool DSF = false, bool PACKED = false>
@@ -613,8 +628,9 @@ static void launch_contract_i(const ElemDesc *desc, const int32_t *elist, int64_
                               const double *tab, const double *mom, double *out, uint32_t *status,
                               double sK, double sM, hipStream_t st)
 {
-    using S = CS<PROB, N, I, J, J + 1, DSF>;
-    const int64_t nitems = count * S::NM_I;
+    using B = BlockItems<PROB, N, I, J, DSF>;
+    using S = typename B::S;
+    const int64_t nitems = count * B::ITEMS;
     const int64_t padded = (nitems + 7) / 8 * 8;
     hipLaunchKernelGGL((k_contract<PROB, N, I, J, DSF, PACKED>), dim3((unsigned)padded), dim3(S::THREADS), 0, st, desc,
                        elist, e0, nitems, padded, tab, mom, out, status, sK, sM);
