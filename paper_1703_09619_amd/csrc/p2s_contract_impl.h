@@ -591,15 +591,15 @@ __device__ __forceinline__ void contract_item(const ElemDesc &d, int64_t e, int 
 
 // One launch per column block (I, J >= I), each kernel holding the code of
 // a single block: the scalar problem, and the vector problem above order 6.
-// The scalar problem's block is diagonal: up to order 6 its items are
+// The scalar problem's block is diagonal: up to order 7 its items are
 // paired like those of the single-launch vector kernel (a whole pair fills
 // NM + 1 slabs' worth of lanes where an unpaired item fills on average half
-// of its workgroup; the scalar N = 6 contraction measured 23 % faster).
-// Orders 7 and 8 stay unpaired: at order 8 a pair needs 576 lanes, more
-// than the 512 of the unpaired workgroup, and order 7 was not measured.
+// of its workgroup; the scalar N = 6 contraction measured 23 % faster, the
+// mixed-order batch 3 % more with order 7 paired too).  Order 8 stays
+// unpaired: a pair needs 576 lanes, more than the unpaired workgroup's 512.
 template <int PROB, int N, int I, int J, bool DSF>
 struct BlockItems {
-    static constexpr bool PAIR = PROB == 0 && N <= 6;
+    static constexpr bool PAIR = PROB == 0 && N <= 7;
     using S = CS<PROB, N, I, J, J + 1, DSF, PAIR>;
     static constexpr int ITEMS = PAIR ? (S::NM_I + 1) / 2 : S::NM_I;
 };
